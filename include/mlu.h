@@ -1,0 +1,156 @@
+/*
+ * mlu -- blocked LU factorization with partial pivoting on AMD Instinct MI355X
+ * (gfx950): the loop-based algorithm variants of Catalan, Herrero,
+ * Quintana-Orti, Rodriguez-Sanchez and van de Geijn, "A Case for Malleable
+ * Thread-Level Linear Algebra Libraries: The LU Factorization with Partial
+ * Pivoting" (arXiv 1611.06365).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Matrices are FP64 and ROW-MAJOR: element (i, j) of an m x n matrix X with
+ *    leading dimension ldx >= max(1, n) is X[i*ldx + j].  (A C-contiguous
+ *    torch tensor of shape (m, n) is such a matrix with ldx = n.)
+ *  * Every pointer whose name starts with d_ / d is DEVICE memory owned by the
+ *    caller; h_ pointers are host memory read during the call only.  The
+ *    library never allocates or frees device memory in these calls.
+ *  * `stream` is a hipStream_t (NULL = the default stream).  All device work is
+ *    enqueued on it asynchronously; nothing synchronizes.  Results (including
+ *    *d_info) are valid once the stream's work has completed.  The look-ahead
+ *    variant additionally uses one library-owned stream per device (default
+ *    priority), forked from and joined back into `stream` with events, so a
+ *    caller's stream capture records the whole call.
+ *  * Return value (synchronous, host-side argument check, LAPACK convention):
+ *      0       the work was enqueued;
+ *      -i      argument i (1-based, `stream` is argument 1) is invalid and
+ *              nothing was enqueued;
+ *      MLU_ERR_HIP  a HIP runtime call failed while enqueuing.
+ *  * Calls that share a workspace must not overlap in time.
+ */
+#ifndef MLU_H
+#define MLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLU_ERR_HIP (-1000)
+
+/* Device-side status written to *d_info (besides 0 and j > 0, see mlu_dgetrf). */
+#define MLU_INFO_SYNC_TIMEOUT (-999)  /* a cross-workgroup wait exceeded its bound */
+#define MLU_INFO_BAD_PIVOT (-998)     /* an interchange index was out of range    */
+
+/* Algorithmic variants (Fig. "LU", Fig. "LU_la_blk", Section 4.2 of the paper). */
+enum mlu_variant {
+  MLU_RL = 0, /* blocked right-looking: RL1 panel, RL2 trsm, RL3 gemm                 */
+  MLU_LL = 1, /* blocked left-looking: LL1 trsm, LL2 gemm, LL3 panel (lazy swaps)     */
+  MLU_LA = 2  /* right-looking with look-ahead: T_PF (PF1-PF3) || T_RU (RU1-RU2)      */
+};
+
+/* Largest panel block held in registers by the diagonal-block kernel. */
+#define MLU_MAX_NB_INNER 32
+
+/* Library version, e.g. 100 for 0.1.0. */
+int mlu_version(void);
+
+/*
+ * Workspace (device bytes) that mlu_dgetrf needs.  Depends on nothing but the
+ * library build; arguments are accepted for forward compatibility.
+ * Returns 0, or -i for an invalid argument; *bytes receives the size.
+ */
+int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t *bytes);
+
+/*
+ * LU factorization with partial pivoting, P A = L U (Section 3, opening;
+ * algorithms of Fig. "LU", Fig. "LU_la_blk" and Section 4.2).
+ *
+ * Precondition:  dA holds A_hat, m x n (any m, n >= 0).
+ * Postcondition: dA holds {L\U}: the strictly lower part of the first min(m,n)
+ *   columns is L (unit diagonal not stored), the upper part of the first
+ *   min(m,n) rows is U; d_ipiv[c] (c < min(m,n)) is the 1-based row interchanged
+ *   with row c+1 at step c (sequential interchanges, LAPACK getrf convention:
+ *   P applies them in order).  Pivot choice: the largest |value| in the current
+ *   column from the diagonal down; the first such row on ties.
+ *   *d_info = 0, or j > 0 if U(j,j) (1-based) is exactly zero (first such j);
+ *   the factorization is still completed, the division by that pivot skipped.
+ *
+ *  stream      hipStream_t.
+ *  m, n        matrix size.
+ *  dA, lda     device matrix, row-major, lda >= max(1, n).
+ *  d_ipiv      device int32[min(m, n)].
+ *  d_info      device int32[1].
+ *  variant     MLU_RL, MLU_LL or MLU_LA.
+ *  nb          outer block size b (>= 1); nb = 1 gives each variant's
+ *              unblocked form, nb >= min(m,n) a single panel.
+ *  nb_inner    block size b_i of the panel factorization, 0..32 (0 = min(nb,
+ *              32)): the panel [A11; A21] is factored by the blocked RL
+ *              algorithm with b_i, each b_i-column block by the
+ *              register-resident unblocked kernel; b_i >= b means LU_unb.
+ *  h_schedule  optional host array of n_schedule block sizes (each >= 1) used
+ *              for the first outer iterations instead of nb (the paper's
+ *              "Determine block size b"; the last block is trimmed to what is
+ *              left of min(m, n)); NULL = constant nb.
+ *  n_schedule  length of h_schedule (ignored when it is NULL).
+ *  iters_limit -1 = run to completion; s >= 0 = stop after s outer loop bodies
+ *              (RL, LL: s panels done; LA: the initial panel and s bodies, so
+ *              panel s is factored and its interchanges are pending outside
+ *              it).  Used to check the loop invariant.
+ *  d_work      device workspace of work_bytes >= mlu_dgetrf_workspace().
+ */
+int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
+               int variant, int nb, int nb_inner, const int32_t *h_schedule, int n_schedule,
+               int iters_limit, void *d_work, size_t work_bytes);
+
+/*
+ * Triangular solve with several right-hand sides, left side, no transpose:
+ * B := T^{-1} B (RL2 / PF1 / RU1 / LL1 use uplo 'L', diag 'U' on trilu(A11),
+ * Fig. "LU").
+ *  uplo   'L' lower or 'U' upper triangle of T is read (the other is ignored).
+ *  diag   'U' unit diagonal (not read) or 'N' stored diagonal.
+ *  m      order of T; nrhs columns of B.  dT (ldt >= max(1,m)), dB (ldb >= max(1,nrhs)).
+ * A zero on a non-unit diagonal gives inf/nan, as in BLAS trsm.
+ */
+int mlu_dtrsm(void *stream, char uplo, char diag, int m, int nrhs, const double *dT, int ldt, double *dB,
+              int ldb);
+
+/*
+ * Solve A X = B with the factorization from mlu_dgetrf (square n x n):
+ * B := U^{-1} L^{-1} P B.  dLU/lda and d_ipiv as returned by mlu_dgetrf; dB is
+ * n x nrhs (ldb >= max(1, nrhs)), overwritten by X.
+ */
+int mlu_dgetrs(void *stream, int n, int nrhs, const double *dLU, int lda, const int32_t *d_ipiv, double *dB,
+               int ldb);
+
+/*
+ * Trailing update C := C - A B (RL3 / PF2 / RU2 / LL2; Fig. "LU", Fig.
+ * "LU_la_blk", Section 4.2) on FP64 matrix cores.  A is m x k, B k x n, C m x n.
+ */
+int mlu_dgemm_update(void *stream, int m, int n, int k, const double *dA, int lda, const double *dB, int ldb,
+                     double *dC, int ldc);
+
+/*
+ * Apply the sequential interchanges d_ipiv[k1 .. k2) (0-based positions,
+ * 1-based row values v with k+1 <= v <= m for position k) to columns
+ * [0, ncols) of the m-row matrix dA (the "row permutations" between the panel
+ * factorization and the update, Section 3.1).  A value out of that range is
+ * skipped and *d_info (if not NULL) is set to MLU_INFO_BAD_PIVOT.
+ */
+int mlu_dlaswp(void *stream, int m, int ncols, double *dA, int lda, int k1, int k2, const int32_t *d_ipiv,
+               int32_t *d_info);
+
+/*
+ * Unblocked factorization of one m x bw block (1 <= bw <= 32, bw <= m): the
+ * diagonal-block kernel (LU_unb of Fig. "LU", left) alone.  Interchanges are
+ * applied inside the block only; d_ipiv[c] (c < bw) receives the 1-based row.
+ * *d_info as in mlu_dgetrf.  Needs bw <= m and the mlu_dgetrf workspace.
+ */
+int mlu_dgetf2_block(void *stream, int m, int bw, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
+                     void *d_work, size_t work_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLU_H */

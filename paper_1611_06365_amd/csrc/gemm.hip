@@ -1,0 +1,182 @@
+// Trailing update C := C - A B on FP64 matrix cores (gfx950).
+//
+// This is the GEMM-shaped step of every variant: RL3 / PF2 / RU2 of the
+// right-looking algorithms and LL2 of the left-looking one (Fig. "LU",
+// Fig. "LU_la_blk", Section 4.2); it carries nearly all of the 2n^3/3 flops.
+//
+// Design (row-major operands, element (i, j) of X at X[i*ldx + j]):
+//  * 128 x 128 C tile per 256-thread workgroup; four wave64s in a 2 x 2 grid,
+//    each owning 64 x 64 of C as 4 x 4 blocks of v_mfma_f64_16x16x4_f64.
+//  * K advances in stages of 16 through double-buffered LDS: the A tile is
+//    kept [i][k] and the B tile [k][j], both straight copies of the row-major
+//    source so global loads stay contiguous 64-byte runs per thread.
+//  * Inside a stage, MFMA step s (0..3) feeds lane group q = lane/16 with
+//    k = 4q + s.  A and B use the same k mapping, so every k is summed exactly
+//    once; lane (i, q) then reads its four A values as one 32-byte LDS run.
+//  * Next stage's global loads are issued before the current stage's MFMAs.
+//  * Workgroup -> tile mapping is XCD-aware: hardware deals workgroups to the
+//    eight XCDs round-robin, so consecutive logical tiles are given to one XCD,
+//    and logical tiles walk 8-tile-row groups so an XCD's L2 sees few A and B
+//    panels at a time.
+#include "mlu_internal.h"
+
+namespace mlu {
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int LDS_A = BK + 2;    // 144-byte row pitch: 16-byte reads of 8 lanes hit distinct banks
+constexpr int LDS_B = BN + 4;    // row pitch offset so lane groups q, q+1 use different banks
+constexpr int GROUP_M = 8;
+
+__device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n;
+  const int nfull = (T / 8) * 8;
+  int t = wg;
+  if (wg < nfull) t = (wg & 7) * (nfull >> 3) + (wg >> 3);
+  const int per_group = GROUP_M * tiles_n;
+  const int group = t / per_group;
+  const int first_m = group * GROUP_M;
+  const int gsz = min(tiles_m - first_m, GROUP_M);
+  const int within = t - group * per_group;
+  tm = first_m + within % gsz;
+  tn = within / gsz;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_update(
+    int m, int n, int k, const double* __restrict__ A, int lda, const double* __restrict__ B,
+    int ldb, double* __restrict__ C, int ldc, int tiles_m, int tiles_n) {
+  __shared__ double As[2][BM * LDS_A];
+  __shared__ double Bs[2][BK * LDS_B];
+
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lq = lane >> 4;
+
+  // global -> register staging: A tile row ar, 8 k's from ac; B tile row br, 8 j's from bc
+  const int ar = tid >> 1, ac = (tid & 1) * 8;
+  const int br = tid >> 4, bc = (tid & 15) * 8;
+  const bool interior_mn = (row0 + BM <= m) && (col0 + BN <= n);
+
+  double ra[8], rb[8];
+  auto gload = [&](int k0) {
+    const bool full = VEC && interior_mn && (k0 + BK <= k);
+    if (full) {
+      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double2 x = pa[e];
+        ra[2 * e] = x.x;
+        ra[2 * e + 1] = x.y;
+        double2 y = pb[e];
+        rb[2 * e] = y.x;
+        rb[2 * e + 1] = y.y;
+      }
+    } else {
+      const int gr = row0 + ar;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + ac + e;
+        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
+      const int gk = k0 + br;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gc = col0 + bc + e;
+        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    double* pa = &As[buf][ar * LDS_A + ac];
+    double* pb = &Bs[buf][br * LDS_B + bc];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      *reinterpret_cast<double2*>(pa + e) = make_double2(ra[e], ra[e + 1]);
+      *reinterpret_cast<double2*>(pb + e) = make_double2(rb[e], rb[e + 1]);
+    }
+  };
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (k + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+
+    double a[4][4], b[4][4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const double* pa = &As[buf][(wm * 64 + blk * 16 + li) * LDS_A + 4 * lq];
+      const double2 a01 = *reinterpret_cast<const double2*>(pa);
+      const double2 a23 = *reinterpret_cast<const double2*>(pa + 2);
+      a[blk][0] = a01.x;
+      a[blk][1] = a01.y;
+      a[blk][2] = a23.x;
+      a[blk][3] = a23.y;
+      const double* pb = &Bs[buf][(4 * lq) * LDS_B + wn * 64 + blk * 16 + li];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) b[blk][s] = pb[s * LDS_B];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Accumulator layout of the 16x16 f64 block (measured on gfx950): lane
+  // (li, lq) holds rows lq + 4*r (r = 0..3) of column li.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
+        const int col = col0 + wn * 64 + j * 16 + li;
+        if (row < m && col < n) {
+          double* pc = C + (size_t)row * ldc + col;
+          *pc = *pc - acc[i][j][r];
+        }
+      }
+}
+
+}  // namespace
+
+hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda,
+                       const double* B, int ldb, double* C, int ldc) {
+  if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
+  const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+  const long long tiles = (long long)tiles_m * tiles_n;
+  if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
+                   (lda % 2 == 0) && (ldb % 2 == 0);
+  if (vec)
+    hipLaunchKernelGGL(k_gemm_update<true>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, A, lda,
+                       B, ldb, C, ldc, tiles_m, tiles_n);
+  else
+    hipLaunchKernelGGL(k_gemm_update<false>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, A,
+                       lda, B, ldb, C, ldc, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+}  // namespace mlu

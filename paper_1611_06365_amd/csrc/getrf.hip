@@ -1,0 +1,343 @@
+// Drivers for the loop-based LU variants and the C ABI (include/mlu.h).
+//
+// Each variant is the paper's loop over an evolving 2x2 / 3x3 partition
+// (FLAME notation); a partition is never copied: every block is a pointer and
+// the leading dimension of the row-major matrix.  For iteration k with j
+// columns done and block size b:
+//   A11 = A + j*lda + j (b x b), A21 = A + (j+b)*lda + j, A12 = A + j*lda + j+b,
+//   A22 = A + (j+b)*lda + j+b.
+//
+//  RL  (Fig. "LU", right)      RL1 panel -> interchanges -> RL2 trsm -> RL3 gemm
+//  LA  (Fig. "LU_la_blk")      interchanges of the pending panel, then
+//                              T_PF {PF1, PF2, PF3} on a second stream while
+//                              T_RU {RU1, RU2} runs on the caller's stream
+//  LL  (Section 4.2)           lazy interchanges of the panel columns, LL1 trsm
+//                              and LL2 gemm block by block, LL3 panel,
+//                              interchanges of the left columns
+//
+// The panel [A11; A21] is itself factored by the blocked RL algorithm with the
+// inner block size b_i <= 32, each b_i-wide block by the register-resident
+// kernel (the paper's outer / inner LU, Section 4.2).
+#include "mlu_internal.h"
+#include "../../include/mlu.h"
+
+#include <mutex>
+#include <vector>
+
+namespace mlu {
+namespace {
+
+__global__ void k_zero(unsigned* p, size_t nwords) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+// one library-owned stream and two events per device for the look-ahead fork
+struct AuxStreams {
+  bool ready = false;
+  hipStream_t s1 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_aux_mu;
+AuxStreams g_aux[64];
+
+hipError_t get_aux(AuxStreams** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  AuxStreams& a = g_aux[dev];
+  if (!a.ready) {
+    if ((e = hipStreamCreateWithFlags(&a.s1, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+    a.ready = true;
+  }
+  *out = &a;
+  return hipSuccess;
+}
+
+#define MLU_TRY(x)                      \
+  do {                                  \
+    hipError_t e__ = (x);               \
+    if (e__ != hipSuccess) return e__;  \
+  } while (0)
+
+struct Ctx {
+  double* A;
+  int lda, m, n;
+  int32_t* ipiv;
+  int32_t* info;
+  int bi;
+  PanelWork* work;
+  double* at(int i, int j) const { return A + (size_t)i * lda + j; }
+};
+
+// RL1 / PF3 / LL3: factor the panel rows j..m-1, columns j..j+b-1 (blocked RL
+// with b_i-wide register-resident blocks); its interchanges are applied to the
+// panel's own columns only.
+hipError_t factor_panel(hipStream_t s, const Ctx& c, int j, int b) {
+  for (int jj = j; jj < j + b; jj += c.bi) {
+    const int bw = (j + b - jj) < c.bi ? (j + b - jj) : c.bi;
+    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work));
+    MLU_TRY(laswp(s, c.A, c.lda, c.m, jj, jj + bw, c.ipiv, j, jj, jj + bw, j + b, c.info));
+    const int rest = j + b - jj - bw;
+    if (rest > 0) {
+      MLU_TRY(trsm_left(s, true, true, bw, rest, c.at(jj, jj), c.lda, c.at(jj, jj + bw), c.lda));
+      MLU_TRY(gemm_update(s, c.m - jj - bw, rest, bw, c.at(jj + bw, jj), c.lda, c.at(jj, jj + bw), c.lda,
+                          c.at(jj + bw, jj + bw), c.lda));
+    }
+  }
+  return hipSuccess;
+}
+
+// RL2 + RL3 (also RU1 + RU2 / PF1 + PF2) on columns [c0, c1) for the panel at j (size b)
+hipError_t update_cols(hipStream_t s, const Ctx& c, int j, int b, int c0, int c1) {
+  if (c1 <= c0) return hipSuccess;
+  MLU_TRY(trsm_left(s, true, true, b, c1 - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
+  if (j + b < c.m)
+    MLU_TRY(gemm_update(s, c.m - j - b, c1 - c0, b, c.at(j + b, j), c.lda, c.at(j, c0), c.lda, c.at(j + b, c0),
+                        c.lda));
+  return hipSuccess;
+}
+
+hipError_t run_rl(hipStream_t s, const Ctx& c, const std::vector<int>& sched, int limit) {
+  int j = 0;
+  for (size_t it = 0; it < sched.size(); ++it) {
+    if (limit >= 0 && (int)it >= limit) break;
+    const int b = sched[it];
+    MLU_TRY(factor_panel(s, c, j, b));                                           // RL1
+    MLU_TRY(laswp(s, c.A, c.lda, c.m, j, j + b, c.ipiv, 0, j, j + b, c.n, c.info));
+    MLU_TRY(update_cols(s, c, j, b, j + b, c.n));                                // RL2, RL3
+    j += b;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, int limit) {
+  AuxStreams* aux = nullptr;
+  MLU_TRY(get_aux(&aux));
+  hipStream_t s1 = aux->s1;
+  if (sched.empty()) return hipSuccess;
+  int b = sched[0];
+  MLU_TRY(factor_panel(s0, c, 0, b));                                            // initial A_BR^P
+  int j = 0;
+  const int mn = c.m < c.n ? c.m : c.n;
+  for (size_t k = 0; j < mn; ++k) {
+    if (limit >= 0 && (int)k >= limit) break;
+    // interchanges of the panel factored last, outside it
+    MLU_TRY(laswp(s0, c.A, c.lda, c.m, j, j + b, c.ipiv, 0, j, j + b, c.n, c.info));
+    const int jn = j + b;
+    const int bp = (k + 1 < sched.size()) ? sched[k + 1] : 0;
+    if (bp > 0) {
+      MLU_TRY(hipEventRecord(aux->fork, s0));
+      MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
+      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp));                            // PF1, PF2
+      MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
+      MLU_TRY(update_cols(s0, c, j, b, jn + bp, c.n));                           // RU1, RU2
+      MLU_TRY(hipEventRecord(aux->join, s1));
+      MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
+    } else {
+      MLU_TRY(update_cols(s0, c, j, b, jn, c.n));                                // RU1, RU2
+    }
+    j = jn;
+    b = bp;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_ll(hipStream_t s, const Ctx& c, const std::vector<int>& sched, int limit) {
+  int j = 0;
+  bool completed = true;
+  for (size_t it = 0; it < sched.size(); ++it) {
+    if (limit >= 0 && (int)it >= limit) {
+      completed = false;
+      break;
+    }
+    const int b = sched[it];
+    // the panel's columns receive every earlier interchange (lazy)
+    MLU_TRY(laswp(s, c.A, c.lda, c.m, 0, j, c.ipiv, j, j + b, 0, 0, c.info));
+    // LL1 and LL2, one earlier panel at a time: X_l := trilu(L_ll)^{-1} B_l,
+    // then every row below panel l (A01 rows and [A11; A21]) -= L_{.,l} X_l
+    int jl = 0;
+    for (size_t l = 0; l < it; ++l) {
+      const int bl = sched[l];
+      MLU_TRY(trsm_left(s, true, true, bl, b, c.at(jl, jl), c.lda, c.at(jl, j), c.lda));
+      MLU_TRY(gemm_update(s, c.m - jl - bl, b, bl, c.at(jl + bl, jl), c.lda, c.at(jl, j), c.lda,
+                          c.at(jl + bl, j), c.lda));
+      jl += bl;
+    }
+    MLU_TRY(factor_panel(s, c, j, b));                                           // LL3
+    MLU_TRY(laswp(s, c.A, c.lda, c.m, j, j + b, c.ipiv, 0, j, 0, 0, c.info));    // left columns
+    j += b;
+  }
+  const int mn = c.m < c.n ? c.m : c.n;
+  if (completed && c.n > mn) {
+    MLU_TRY(laswp(s, c.A, c.lda, c.m, 0, mn, c.ipiv, mn, c.n, 0, 0, c.info));
+    MLU_TRY(trsm_left(s, true, true, mn, c.n - mn, c.A, c.lda, c.at(0, mn), c.lda));
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes) {
+  const size_t nw = bytes / 4;
+  if (nw == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, (unsigned*)p, nw);
+  return hipGetLastError();
+}
+
+}  // namespace mlu
+
+using namespace mlu;
+
+extern "C" {
+
+int mlu_version(void) { return 100; }
+
+int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t* bytes) {
+  if (m < 0) return -1;
+  if (n < 0) return -2;
+  if (variant < MLU_RL || variant > MLU_LA) return -3;
+  if (nb < 1) return -4;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -5;
+  if (!bytes) return -6;
+  *bytes = workspace_bytes();
+  return 0;
+}
+
+int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+               int nb, int nb_inner, const int32_t* h_schedule, int n_schedule, int iters_limit, void* d_work,
+               size_t work_bytes) {
+  const int mn = m < n ? m : n;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (mn > 0 && !dA) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (mn > 0 && !d_ipiv) return -6;
+  if (!d_info) return -7;
+  if (variant < MLU_RL || variant > MLU_LA) return -8;
+  if (nb < 1) return -9;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
+  if (h_schedule) {
+    if (n_schedule < 1) return -12;
+    for (int i = 0; i < n_schedule; ++i)
+      if (h_schedule[i] < 1) return -11;
+  }
+  if (iters_limit < -1) return -13;
+  if (!d_work) return -14;
+  if (work_bytes < workspace_bytes()) return -15;
+  if (m > kPanelMaxWG * 1024) return -2;
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
+  if (mn == 0) return 0;
+  if (zero_bytes(s, d_work, sizeof(GridBar)) != hipSuccess) return MLU_ERR_HIP;
+
+  std::vector<int> sched;
+  int j = 0;
+  for (int i = 0; h_schedule && i < n_schedule && j < mn; ++i) {
+    const int b = h_schedule[i] < mn - j ? h_schedule[i] : mn - j;
+    sched.push_back(b);
+    j += b;
+  }
+  while (j < mn) {
+    const int b = nb < mn - j ? nb : mn - j;
+    sched.push_back(b);
+    j += b;
+  }
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, reinterpret_cast<PanelWork*>(d_work)};
+  c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
+
+  hipError_t e;
+  if (variant == MLU_RL) e = run_rl(s, c, sched, iters_limit);
+  else if (variant == MLU_LA) e = run_la(s, c, sched, iters_limit);
+  else e = run_ll(s, c, sched, iters_limit);
+  return e == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+int mlu_dtrsm(void* stream, char uplo, char diag, int m, int nrhs, const double* dT, int ldt, double* dB,
+              int ldb) {
+  const bool lower = uplo == 'L' || uplo == 'l';
+  const bool upper = uplo == 'U' || uplo == 'u';
+  const bool unit = diag == 'U' || diag == 'u';
+  const bool nonunit = diag == 'N' || diag == 'n';
+  if (!lower && !upper) return -2;
+  if (!unit && !nonunit) return -3;
+  if (m < 0) return -4;
+  if (nrhs < 0) return -5;
+  if (m > 0 && !dT) return -6;
+  if (ldt < (m > 1 ? m : 1)) return -7;
+  if (m > 0 && nrhs > 0 && !dB) return -8;
+  if (ldb < (nrhs > 1 ? nrhs : 1)) return -9;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return trsm_left(s, lower, unit, m, nrhs, dT, ldt, dB, ldb) == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+int mlu_dgetrs(void* stream, int n, int nrhs, const double* dLU, int lda, const int32_t* d_ipiv, double* dB,
+               int ldb) {
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (n > 0 && !dLU) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && !d_ipiv) return -6;
+  if (n > 0 && nrhs > 0 && !dB) return -7;
+  if (ldb < (nrhs > 1 ? nrhs : 1)) return -8;
+  if (n == 0 || nrhs == 0) return 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (laswp(s, dB, ldb, n, 0, n, d_ipiv, 0, nrhs, 0, 0, nullptr) != hipSuccess) return MLU_ERR_HIP;
+  if (trsm_left(s, true, true, n, nrhs, dLU, lda, dB, ldb) != hipSuccess) return MLU_ERR_HIP;
+  if (trsm_left(s, false, false, n, nrhs, dLU, lda, dB, ldb) != hipSuccess) return MLU_ERR_HIP;
+  return 0;
+}
+
+int mlu_dgemm_update(void* stream, int m, int n, int k, const double* dA, int lda, const double* dB, int ldb,
+                     double* dC, int ldc) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (k < 0) return -4;
+  if (m > 0 && k > 0 && !dA) return -5;
+  if (lda < (k > 1 ? k : 1)) return -6;
+  if (k > 0 && n > 0 && !dB) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (m > 0 && n > 0 && !dC) return -9;
+  if (ldc < (n > 1 ? n : 1)) return -10;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return gemm_update(s, m, n, k, dA, lda, dB, ldb, dC, ldc) == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+int mlu_dlaswp(void* stream, int m, int ncols, double* dA, int lda, int k1, int k2, const int32_t* d_ipiv,
+               int32_t* d_info) {
+  if (m < 0) return -2;
+  if (ncols < 0) return -3;
+  if (m > 0 && ncols > 0 && !dA) return -4;
+  if (lda < (ncols > 1 ? ncols : 1)) return -5;
+  if (k1 < 0 || k1 > m) return -6;
+  if (k2 < k1 || k2 > m) return -7;
+  if (k2 > k1 && !d_ipiv) return -8;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return laswp(s, dA, lda, m, k1, k2, d_ipiv, 0, ncols, 0, 0, d_info) == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info,
+                     void* d_work, size_t work_bytes) {
+  if (m < 0 || m > kPanelMaxWG * 1024) return -2;
+  if (bw < 0 || bw > MLU_MAX_NB_INNER || bw > m) return -3;
+  if (bw > 0 && !dA) return -4;
+  if (lda < (bw > 1 ? bw : 1)) return -5;
+  if (bw > 0 && !d_ipiv) return -6;
+  if (!d_info) return -7;
+  if (!d_work) return -8;
+  if (work_bytes < workspace_bytes()) return -9;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
+  if (bw == 0) return 0;
+  if (zero_bytes(s, d_work, sizeof(GridBar)) != hipSuccess) return MLU_ERR_HIP;
+  return panel_factor(s, dA, lda, m, bw, 0, d_ipiv, d_info, reinterpret_cast<PanelWork*>(d_work)) == hipSuccess
+             ? 0
+             : MLU_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+"""ctypes binding of libmlu (include/mlu.h): argument marshalling only.
+
+Every function here has the name and argument order of the C entry point; the
+helpers at the bottom only turn torch tensors into pointers, sizes and the
+current HIP stream.  All computation happens in the HIP kernels of libmlu.so;
+if the library is not built this module raises on import of any entry point.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlu.so")
+
+MLU_RL, MLU_LL, MLU_LA = 0, 1, 2
+VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA}
+MLU_ERR_HIP = -1000
+MLU_INFO_SYNC_TIMEOUT = -999
+MLU_INFO_BAD_PIVOT = -998
+MLU_MAX_NB_INNER = 32
+
+_vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
+
+_SIGNATURES = {
+    "mlu_version": ([], _i),
+    "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
+    "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dtrsm": ([_vp, _c, _c, _i, _i, _vp, _i, _vp, _i], _i),
+    "mlu_dgetrs": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i], _i),
+    "mlu_dgemm_update": ([_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i], _i),
+    "mlu_dlaswp": ([_vp, _i, _i, _vp, _i, _i, _i, _vp, _vp], _i),
+    "mlu_dgetf2_block": ([_vp, _i, _i, _vp, _i, _vp, _vp, _vp, _sz], _i),
+}
+EXPORTED = tuple(_SIGNATURES)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmlu.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        try:  # bind to the HIP runtime torch already carries (same soname)
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(path):
+            raise OSError(f"libmlu.so not found at {path}; run paper_1611_06365_amd/build.py")
+        lib = ctypes.CDLL(path)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _call(name, *args):
+    return getattr(load(), name)(*args)
+
+
+# ---------------------------------------------------------------- C entry points
+def mlu_version() -> int:
+    return _call("mlu_version")
+
+
+def mlu_dgetrf_workspace(m, n, variant, nb, nb_inner) -> tuple[int, int]:
+    out = _sz(0)
+    rc = _call("mlu_dgetrf_workspace", m, n, variant, nb, nb_inner, ctypes.byref(out))
+    return rc, out.value
+
+
+def mlu_dgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_schedule, n_schedule,
+               iters_limit, d_work, work_bytes) -> int:
+    return _call("mlu_dgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_schedule,
+                 n_schedule, iters_limit, d_work, work_bytes)
+
+
+def mlu_dtrsm(stream, uplo, diag, m, nrhs, dT, ldt, dB, ldb) -> int:
+    return _call("mlu_dtrsm", stream, uplo, diag, m, nrhs, dT, ldt, dB, ldb)
+
+
+def mlu_dgetrs(stream, n, nrhs, dLU, lda, d_ipiv, dB, ldb) -> int:
+    return _call("mlu_dgetrs", stream, n, nrhs, dLU, lda, d_ipiv, dB, ldb)
+
+
+def mlu_dgemm_update(stream, m, n, k, dA, lda, dB, ldb, dC, ldc) -> int:
+    return _call("mlu_dgemm_update", stream, m, n, k, dA, lda, dB, ldb, dC, ldc)
+
+
+def mlu_dlaswp(stream, m, ncols, dA, lda, k1, k2, d_ipiv, d_info) -> int:
+    return _call("mlu_dlaswp", stream, m, ncols, dA, lda, k1, k2, d_ipiv, d_info)
+
+
+def mlu_dgetf2_block(stream, m, bw, dA, lda, d_ipiv, d_info, d_work, work_bytes) -> int:
+    return _call("mlu_dgetf2_block", stream, m, bw, dA, lda, d_ipiv, d_info, d_work, work_bytes)
+
+
+# ---------------------------------------------------------------- torch marshalling
+class MluError(RuntimeError):
+    pass
+
+
+def check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise MluError(f"{what} returned {rc}")
+
+
+def _stream(stream=None) -> int:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _rowmajor(t, name):
+    import torch
+
+    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D float64 CUDA tensor with unit column stride")
+    return t.data_ptr(), max(1, t.stride(0))
+
+
+def _i32(t, name, n):
+    import torch
+
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{name} must be a contiguous int32 CUDA tensor with >= {n} entries")
+    return t.data_ptr()
+
+
+def workspace(device=None):
+    """A device workspace tensor large enough for mlu_dgetrf."""
+    import torch
+
+    rc, nbytes = mlu_dgetrf_workspace(1, 1, MLU_RL, 1, 0)
+    check(rc, "mlu_dgetrf_workspace")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ipiv=None, info=None,
+          work=None, stream=None):
+    """Factor A (m x n float64 CUDA tensor, row-major) in place; returns (ipiv, info) tensors.
+
+    No synchronization: read info after the stream has finished.
+    """
+    import torch
+
+    pa, lda = _rowmajor(A, "A")
+    m, n = A.shape
+    k = min(m, n)
+    ipiv = torch.empty(max(k, 1), dtype=torch.int32, device=A.device) if ipiv is None else ipiv
+    info = torch.empty(1, dtype=torch.int32, device=A.device) if info is None else info
+    work = workspace(A.device) if work is None else work
+    sched = None
+    nsched = 0
+    if schedule is not None:
+        arr = (ctypes.c_int32 * len(schedule))(*[int(b) for b in schedule])
+        sched, nsched = ctypes.cast(arr, ctypes.c_void_p), len(schedule)
+    v = VARIANT_IDS[variant] if isinstance(variant, str) else int(variant)
+    rc = mlu_dgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
+                    nb_inner, sched, nsched, iters_limit, work.data_ptr(), work.numel())
+    check(rc, "mlu_dgetrf")
+    return ipiv, info
+
+
+def trsm(T, B, uplo="L", diag="U", stream=None):
+    pt, ldt = _rowmajor(T, "T")
+    pb, ldb = _rowmajor(B, "B")
+    rc = mlu_dtrsm(_stream(stream), uplo.encode(), diag.encode(), T.shape[0], B.shape[1], pt, ldt, pb, ldb)
+    check(rc, "mlu_dtrsm")
+
+
+def getrs(LU, ipiv, B, stream=None):
+    pa, lda = _rowmajor(LU, "LU")
+    pb, ldb = _rowmajor(B, "B")
+    n = LU.shape[0]
+    rc = mlu_dgetrs(_stream(stream), n, B.shape[1], pa, lda, _i32(ipiv, "ipiv", n), pb, ldb)
+    check(rc, "mlu_dgetrs")
+
+
+def gemm_update(C, A, B, stream=None):
+    pc, ldc = _rowmajor(C, "C")
+    pa, lda = _rowmajor(A, "A")
+    pb, ldb = _rowmajor(B, "B")
+    m, k = A.shape
+    n = B.shape[1]
+    rc = mlu_dgemm_update(_stream(stream), m, n, k, pa, lda, pb, ldb, pc, ldc)
+    check(rc, "mlu_dgemm_update")
+
+
+def laswp(A, k1, k2, ipiv, info=None, stream=None):
+    pa, lda = _rowmajor(A, "A")
+    pinfo = info.data_ptr() if info is not None else None
+    rc = mlu_dlaswp(_stream(stream), A.shape[0], A.shape[1], pa, lda, k1, k2, _i32(ipiv, "ipiv", k2), pinfo)
+    check(rc, "mlu_dlaswp")
+
+
+def getf2_block(A, ipiv=None, info=None, work=None, stream=None):
+    import torch
+
+    pa, lda = _rowmajor(A, "A")
+    m, bw = A.shape
+    ipiv = torch.empty(max(bw, 1), dtype=torch.int32, device=A.device) if ipiv is None else ipiv
+    info = torch.empty(1, dtype=torch.int32, device=A.device) if info is None else info
+    work = workspace(A.device) if work is None else work
+    rc = mlu_dgetf2_block(_stream(stream), m, bw, pa, lda, _i32(ipiv, "ipiv", bw), _i32(info, "info", 1),
+                          work.data_ptr(), work.numel())
+    check(rc, "mlu_dgetf2_block")
+    return ipiv, info

@@ -1,0 +1,85 @@
+"""The C-ABI library loads and exports every symbol include/mlu.h declares;
+host-side argument checks reject bad arguments before any device work.
+CPU only: no call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_06365_amd import mlu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlu.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlu_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mlu.LIB_PATH):
+        from paper_1611_06365_amd import build
+
+        build.build()
+    return mlu.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mlu_dgetrf", "mlu_dgetrf_workspace", "mlu_dtrsm", "mlu_dgetrs", "mlu_dgemm_update",
+                     "mlu_dlaswp", "mlu_dgetf2_block", "mlu_version"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(mlu.EXPORTED)
+
+
+def test_version_and_workspace(lib):
+    assert mlu.mlu_version() == 100
+    rc, nbytes = mlu.mlu_dgetrf_workspace(16384, 16384, mlu.MLU_LA, 256, 32)
+    assert rc == 0 and 0 < nbytes <= 1 << 20
+    assert mlu.mlu_dgetrf_workspace(-1, 4, 0, 1, 0)[0] == -1
+    assert mlu.mlu_dgetrf_workspace(4, 4, 7, 1, 0)[0] == -3
+    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 0, 0)[0] == -4
+    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 33)[0] == -5
+
+
+def _getrf(**kw):
+    args = dict(stream=None, m=8, n=8, dA=1024, lda=8, d_ipiv=2048, d_info=4096, variant=0, nb=4, nb_inner=0,
+                h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8192, work_bytes=1 << 20)
+    args.update(kw)
+    return mlu.mlu_dgetrf(*args.values())
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(m=-1), -2), (dict(n=-3), -3), (dict(dA=None), -4), (dict(lda=7), -5), (dict(d_ipiv=None), -6),
+    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=33), -10),
+    (dict(nb_inner=-1), -10), (dict(iters_limit=-2), -13), (dict(d_work=None), -14), (dict(work_bytes=16), -15),
+])
+def test_getrf_argument_checks(lib, kw, code):
+    assert _getrf(**kw) == code
+
+
+def test_getrf_bad_schedule(lib):
+    arr = (ctypes.c_int32 * 3)(4, 0, 4)
+    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=3) == -11
+    arr = (ctypes.c_int32 * 1)(4)
+    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=0) == -12
+
+
+def test_other_argument_checks(lib):
+    assert mlu.mlu_dtrsm(None, b"X", b"U", 4, 4, 1024, 4, 2048, 4) == -2
+    assert mlu.mlu_dtrsm(None, b"L", b"Q", 4, 4, 1024, 4, 2048, 4) == -3
+    assert mlu.mlu_dtrsm(None, b"L", b"U", 4, 4, 1024, 3, 2048, 4) == -7
+    assert mlu.mlu_dgetrs(None, 4, 2, 1024, 3, 2048, 4096, 2) == -5
+    assert mlu.mlu_dgemm_update(None, 4, 4, 4, 1024, 3, 2048, 4, 4096, 4) == -6
+    assert mlu.mlu_dlaswp(None, 4, 4, 1024, 4, 2, 1, 2048, None) == -7
+    assert mlu.mlu_dgetf2_block(None, 8, 33, 1024, 33, 2048, 4096, 8192, 1 << 20) == -3
+    assert mlu.mlu_dgetf2_block(None, 4, 8, 1024, 8, 2048, 4096, 8192, 1 << 20) == -3
