@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 blocked LU with partial pivoting on one MI355X.
+
+A step is one whole factorization P A = L U of an n x n matrix (every step of
+the hot path: panel factorizations, row interchanges, triangular solves and
+trailing updates) through the C ABI.  Inputs are synthetic and seeded:
+A = B B^T + n I with B ~ N(0, 1) (default) or U(0, 1) entries, generated on the
+GPU; one pristine copy per step is resident in HBM before the timed region, so
+the timed region contains factorizations only.
+
+Prints ONE JSON line.  `value` is GFLOP/s = (2 n^3 / 3) / (seconds per step).
+`roofline` covers the dominant kernel (the outer trailing-update GEMM), timed
+with HIP events around each of its launches inside the timed region.
+`cpu_baseline` times the plain C oracle on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GFLOP/s & %MFMA roofline at n=16384 (FP64 vs mixed+refine @1e-13); batched ops/s"
+FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_trailing_n16384_traffic.md")
+GEMM_SRC = os.path.join(ROOT, "paper_1611_06365_amd", "csrc", "gemm.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sampled_residual(A, F, ipiv, nsamp=512, seed=0):
+    """max |(P A)[i,j] - sum_k L[i,k] U[k,j]| / max|A| over random (i, j)."""
+    import numpy as np
+    import torch
+
+    n = A.shape[0]
+    piv = ipiv.cpu().numpy().astype(np.int64) - 1
+    perm = np.arange(n)
+    for c in range(n):
+        p = piv[c]
+        perm[c], perm[p] = perm[p], perm[c]
+    rng = np.random.default_rng(seed)
+    ii = torch.from_numpy(rng.integers(0, n, nsamp)).to(A.device)
+    jj = torch.from_numpy(rng.integers(0, n, nsamp)).to(A.device)
+    pa = A[torch.from_numpy(perm).to(A.device)[ii], jj]
+    Lrows = F[ii, :].clone()
+    Ucols = F[:, jj].T.clone()
+    k = torch.arange(n, device=A.device)
+    Lrows = torch.where(k[None, :] < ii[:, None], Lrows, torch.zeros_like(Lrows))
+    Lrows[torch.arange(nsamp, device=A.device), ii] = 1.0
+    Ucols = torch.where(k[None, :] <= jj[:, None], Ucols, torch.zeros_like(Ucols))
+    lu = (Lrows * Ucols).sum(dim=1)
+    return float((pa - lu).abs().max() / A.abs().max())
+
+
+def traffic_record():
+    """Per-launch HBM bytes of the trailing GEMM from the committed rocprofv3
+    counter summary, or None if missing or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    m = re.search(r"TRAFFIC_JSON:\s*(\{.*\})", open(TRAFFIC_FILE).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sha = hashlib.sha1(open(GEMM_SRC, "rb").read()).hexdigest()
+    if rec.get("source_sha1") != sha:
+        return None
+    return rec
+
+
+def cpu_baseline(n: int):
+    import numpy as np
+
+    import inputs
+    from oracle import c_oracle
+
+    c_oracle.build(force=False)
+    A = inputs.spd_bbt(n, seed=0)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ipiv, info = c_oracle.dgetrf_rl(A, nb=64)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round((2.0 * n ** 3 / 3.0) / dt / 1e9, 3),
+        "unit": "GFLOP/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"plain C blocked-RL oracle (nb=64, OpenMP) factoring one n={n} A=B B^T+nI matrix "
+                  f"(seed 0) in {dt:.2f} s; the n=16384 workload is ~{(16384 / n) ** 3:.0f}x the flops",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--variant", default="la", choices=["rl", "ll", "la"])
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--nb-inner", type=int, default=16)
+    ap.add_argument("--matrix", default="spd", choices=["spd", "uniform"])
+    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build factors one matrix per GPU and has no "
+              "multi-GPU path (see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import inputs.device as D
+    from paper_1611_06365_amd import mlu
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mlu.load()
+    dev = torch.device("cuda:0")
+    n, K, W = args.n, args.steps, args.warmup
+    flops = 2.0 * n ** 3 / 3.0
+
+    log(f"generating {args.matrix} n={n} and {K + W + 1} resident copies")
+    A = D.spd_bbt(n, seed=0, device=dev) if args.matrix == "spd" else D.uniform01(n, seed=0, device=dev)
+    copies = [A.clone() for _ in range(K + W)]
+    work = mlu.workspace(dev)
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step(M):
+        mlu.getrf(M, variant=args.variant, nb=args.nb, nb_inner=args.nb_inner, ipiv=ipiv, info=info, work=work)
+
+    check = {}
+    for w in range(W):
+        step(copies[w])
+        torch.cuda.synchronize()
+        if w == 0:
+            check = {"info": int(info.item()),
+                     "sampled_residual": sampled_residual(A, copies[0], ipiv)}
+            log(f"warmup 0 done: {check}")
+    if W == 0:
+        log("no warmup: correctness check skipped")
+
+    torch.cuda.synchronize()
+    rc = mlu.mlu_trace_begin(4096)
+    mlu.check(rc, "mlu_trace_begin")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(K):
+        step(copies[W + i])
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    rc, launches, gemm_ms, gemm_flops, gemm_bytes = mlu.mlu_trace_end()
+    mlu.check(rc, "mlu_trace_end")
+    ms_step = ms / K
+    value = flops / (ms_step / 1e3) / 1e9
+    log(f"timed {K} steps: {ms_step:.3f} ms/step (wall {wall / K * 1e3:.3f}), {value:.1f} GFLOP/s")
+    if K > 0 and W > 0:
+        check["info_last"] = int(info.item())
+
+    roof = None
+    if launches > 0:
+        per_launch_flops = gemm_flops / launches
+        per_launch_s = gemm_ms / launches / 1e3
+        achieved = per_launch_flops / per_launch_s / 1e12
+        rec = traffic_record() if (n == 16384 and args.nb == 256 and args.variant == "la") else None
+        traffic = None
+        if rec is not None:
+            traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        roof = {
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel": "k_gemm_trailing (RL3/PF2/RU2 trailing update, v_mfma_f64_16x16x4)",
+            "launches": launches,
+            "avg_launch_us": round(gemm_ms / launches * 1e3, 3),
+            "algorithmic_flops_per_launch": per_launch_flops,
+            "algorithmic_bytes_per_launch": gemm_bytes / launches,
+            "share_of_step_time": round(gemm_ms / ms, 4),
+        }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: C oracle on n={args.cpu_n}")
+        cpu = cpu_baseline(args.cpu_n)
+        log(f"cpu baseline: {cpu['value']} GFLOP/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"getrf FP64 n={n} {'A=B*B^T+n*I, B~N(0,1)' if args.matrix == 'spd' else 'U(0,1)'} "
+                        f"(seed 0), variant={args.variant.upper()}, nb={args.nb}, nb_inner={args.nb_inner}",
+            "n": n,
+            "variant": args.variant,
+            "nb": args.nb,
+            "nb_inner": args.nb_inner,
+            "matrix": args.matrix,
+            "parallelism": "single GPU",
+        },
+        "frac_fp64_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -50,7 +50,7 @@ enum mlu_variant {
 };
 
 /* Largest panel block held in registers by the diagonal-block kernel. */
-#define MLU_MAX_NB_INNER 32
+#define MLU_MAX_NB_INNER 16
 
 /* Library version, e.g. 100 for 0.1.0. */
 int mlu_version(void);
@@ -78,14 +78,15 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
  *
  *  stream      hipStream_t.
  *  m, n        matrix size.
- *  dA, lda     device matrix, row-major, lda >= max(1, n).
+ *  dA, lda     device matrix, row-major, lda >= max(1, n); m <= 32768 (the
+ *              tallest panel the register-resident kernel holds).
  *  d_ipiv      device int32[min(m, n)].
  *  d_info      device int32[1].
  *  variant     MLU_RL, MLU_LL or MLU_LA.
  *  nb          outer block size b (>= 1); nb = 1 gives each variant's
  *              unblocked form, nb >= min(m,n) a single panel.
- *  nb_inner    block size b_i of the panel factorization, 0..32 (0 = min(nb,
- *              32)): the panel [A11; A21] is factored by the blocked RL
+ *  nb_inner    block size b_i of the panel factorization, 0..16 (0 = min(nb,
+ *              16)): the panel [A11; A21] is factored by the blocked RL
  *              algorithm with b_i, each b_i-column block by the
  *              register-resident unblocked kernel; b_i >= b means LU_unb.
  *  h_schedule  optional host array of n_schedule block sizes (each >= 1) used
@@ -141,13 +142,27 @@ int mlu_dlaswp(void *stream, int m, int ncols, double *dA, int lda, int k1, int 
                int32_t *d_info);
 
 /*
- * Unblocked factorization of one m x bw block (1 <= bw <= 32, bw <= m): the
+ * Unblocked factorization of one m x bw block (1 <= bw <= 16, bw <= m): the
  * diagonal-block kernel (LU_unb of Fig. "LU", left) alone.  Interchanges are
  * applied inside the block only; d_ipiv[c] (c < bw) receives the 1-based row.
  * *d_info as in mlu_dgetrf.  Needs bw <= m and the mlu_dgetrf workspace.
  */
 int mlu_dgetf2_block(void *stream, int m, int bw, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
                      void *d_work, size_t work_bytes);
+
+/*
+ * Measurement hook: event timing of the outer trailing-update GEMM launches
+ * (RL3, PF2, RU2 -- the kernel that carries nearly all of the flops).
+ * mlu_trace_begin(capacity) makes every following such launch, on any stream,
+ * record a pair of HIP events around itself (at most `capacity` launches; the
+ * library creates the events once).  mlu_trace_end waits for the recorded
+ * events and returns the number of launches timed, their summed duration in
+ * ms, and their algorithmic flops (2 m n k per launch) and bytes
+ * (8 (2 m n + m k + k n) per launch); it stops the recording.  Process-wide
+ * state: not for use while another thread factors.
+ */
+int mlu_trace_begin(int capacity);
+int mlu_trace_end(int *launches, double *total_ms, double *flops, double *bytes);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@ from .matrices import (  # noqa: F401
     wilkinson_growth,
     known_answer,
     zero_column,
+    leader_perm,
     random_schedule,
     small_int_matrix,
 )

@@ -64,8 +64,11 @@ def wilkinson_growth(n: int) -> np.ndarray:
     return np.ascontiguousarray(w)
 
 
-def known_answer(m: int, n: int | None = None, seed: int = 0):
+def known_answer(m: int, n: int | None = None, seed: int = 0, perm=None):
     """Return (A, perm, L, U) with A[perm[i], :] = (L @ U)[i, :].
+
+    `perm` (optional) fixes where each row of L U lands; by default it is a
+    seeded random permutation.
 
     L is m x k unit lower trapezoidal (k = min(m, n)) with off-diagonal entries
     in {-7/8, ..., 7/8}; U is k x n upper trapezoidal with integer entries in
@@ -82,7 +85,7 @@ def known_answer(m: int, n: int | None = None, seed: int = 0):
     U = np.triu(rng.integers(-8, 9, (k, n)).astype(np.float64))
     d = rng.integers(1, 9, k) * rng.choice([-1.0, 1.0], k)
     U[np.arange(k), np.arange(k)] = d
-    perm = rng.permutation(m)
+    perm = rng.permutation(m) if perm is None else np.asarray(perm, dtype=np.int64)
     LU = L @ U
     A = np.empty((m, n))
     A[perm, :] = LU
@@ -109,6 +112,22 @@ def zero_column(n: int, seed: int = 0, col: int = 0):
     A = np.empty((n, n))
     A[perm, :] = L @ U
     return np.ascontiguousarray(A)
+
+
+def leader_perm(m: int, k: int, split: int, fail_at, seed: int = 0):
+    """A permutation whose first k entries lie below `split`, except entry
+    `fail_at` (if not None), which lies at or above it."""
+    rng = _rng(seed, 17)
+    low = rng.permutation(split)
+    high = split + rng.permutation(m - split)
+    head = list(low[:k])
+    if fail_at is not None:
+        head[fail_at] = high[0]
+        rest = list(low[k:]) + list(high[1:]) + [low[fail_at]]
+    else:
+        rest = list(low[k:]) + list(high)
+    rest = list(rng.permutation(np.array(rest)))
+    return np.array(head + rest, dtype=np.int64)
 
 
 def small_int_matrix(m: int, n: int, seed: int = 0, lo: int = -3, hi: int = 3) -> np.ndarray:

@@ -20,6 +20,9 @@
 //    panels at a time.
 #include "mlu_internal.h"
 
+#include <mutex>
+#include <vector>
+
 namespace mlu {
 namespace {
 
@@ -43,9 +46,9 @@ __device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, in
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(256, 2) void k_gemm_update(
-    int m, int n, int k, const double* __restrict__ A, int lda, const double* __restrict__ B,
-    int ldb, double* __restrict__ C, int ldc, int tiles_m, int tiles_n) {
+__device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __restrict__ A, int lda,
+                                          const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                          int ldc, int tiles_m, int tiles_n) {
   __shared__ double As[2][BM * LDS_A];
   __shared__ double Bs[2][BK * LDS_B];
 
@@ -160,23 +163,104 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(
       }
 }
 
+// Generic launches (inner panel updates, blocked triangular solves) and the
+// outer trailing updates (RL3, PF2, RU2) run the same body under two kernel
+// names, so that a kernel trace separates the dominant launches.
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_update(int m, int n, int k, const double* __restrict__ A,
+                                                        int lda, const double* __restrict__ B, int ldb,
+                                                        double* __restrict__ C, int ldc, int tiles_m,
+                                                        int tiles_n) {
+  gemm_body<VEC>(m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+}
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, const double* __restrict__ A,
+                                                          int lda, const double* __restrict__ B, int ldb,
+                                                          double* __restrict__ C, int ldc, int tiles_m,
+                                                          int tiles_n) {
+  gemm_body<VEC>(m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+}
+
+// Event timing of the outer trailing-update launches (see mlu_trace_begin).
+struct Trace {
+  std::mutex mu;
+  bool on = false;
+  int cap = 0, used = 0;
+  std::vector<hipEvent_t> ev;
+  double flops = 0.0, bytes = 0.0;
+};
+Trace g_trace;
+
 }  // namespace
 
-hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda,
-                       const double* B, int ldb, double* C, int ldc) {
+hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                       double* C, int ldc, bool trailing) {
   if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
   const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
   const long long tiles = (long long)tiles_m * tiles_n;
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
   const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
                    (lda % 2 == 0) && (ldb % 2 == 0);
-  if (vec)
-    hipLaunchKernelGGL(k_gemm_update<true>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, A, lda,
-                       B, ldb, C, ldc, tiles_m, tiles_n);
-  else
-    hipLaunchKernelGGL(k_gemm_update<false>, dim3((unsigned)tiles), dim3(256), 0, s, m, n, k, A,
-                       lda, B, ldb, C, ldc, tiles_m, tiles_n);
-  return hipGetLastError();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (trailing) {
+    std::lock_guard<std::mutex> lk(g_trace.mu);
+    if (g_trace.on && g_trace.used < g_trace.cap) {
+      e0 = g_trace.ev[2 * g_trace.used];
+      e1 = g_trace.ev[2 * g_trace.used + 1];
+      ++g_trace.used;
+      g_trace.flops += 2.0 * m * (double)n * k;
+      g_trace.bytes += 8.0 * (2.0 * m * (double)n + (double)m * k + (double)k * n);
+    }
+  }
+  if (e0) {
+    hipError_t e = hipEventRecord(e0, s);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((unsigned)tiles), block(256);
+  if (trailing) {
+    if (vec) hipLaunchKernelGGL(k_gemm_trailing<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    else hipLaunchKernelGGL(k_gemm_trailing<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+  } else {
+    if (vec) hipLaunchKernelGGL(k_gemm_update<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    else hipLaunchKernelGGL(k_gemm_update<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+  return e;
+}
+
+hipError_t trace_begin(int capacity) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  while ((int)g_trace.ev.size() < 2 * capacity) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    g_trace.ev.push_back(e);
+  }
+  g_trace.cap = capacity;
+  g_trace.used = 0;
+  g_trace.flops = g_trace.bytes = 0.0;
+  g_trace.on = true;
+  return hipSuccess;
+}
+
+hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  g_trace.on = false;
+  double total = 0.0;
+  for (int i = 0; i < g_trace.used; ++i) {
+    hipError_t r = hipEventSynchronize(g_trace.ev[2 * i + 1]);
+    if (r != hipSuccess) return r;
+    float t = 0.f;
+    r = hipEventElapsedTime(&t, g_trace.ev[2 * i], g_trace.ev[2 * i + 1]);
+    if (r != hipSuccess) return r;
+    total += t;
+  }
+  *launches = g_trace.used;
+  *ms = total;
+  *flops = g_trace.flops;
+  *bytes = g_trace.bytes;
+  return hipSuccess;
 }
 
 }  // namespace mlu

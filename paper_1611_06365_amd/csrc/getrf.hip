@@ -71,6 +71,7 @@ struct Ctx {
   int32_t* info;
   int bi;
   PanelWork* work;
+  unsigned* epoch;   // panel launch counter of this call (panels run one at a time)
   double* at(int i, int j) const { return A + (size_t)i * lda + j; }
 };
 
@@ -80,7 +81,7 @@ struct Ctx {
 hipError_t factor_panel(hipStream_t s, const Ctx& c, int j, int b) {
   for (int jj = j; jj < j + b; jj += c.bi) {
     const int bw = (j + b - jj) < c.bi ? (j + b - jj) : c.bi;
-    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work));
+    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch));
     MLU_TRY(laswp(s, c.A, c.lda, c.m, jj, jj + bw, c.ipiv, j, jj, jj + bw, j + b, c.info));
     const int rest = j + b - jj - bw;
     if (rest > 0) {
@@ -98,7 +99,7 @@ hipError_t update_cols(hipStream_t s, const Ctx& c, int j, int b, int c0, int c1
   MLU_TRY(trsm_left(s, true, true, b, c1 - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
   if (j + b < c.m)
     MLU_TRY(gemm_update(s, c.m - j - b, c1 - c0, b, c.at(j + b, j), c.lda, c.at(j, c0), c.lda, c.at(j + b, c0),
-                        c.lda));
+                        c.lda, /*trailing=*/true));
   return hipSuccess;
 }
 
@@ -229,12 +230,12 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   if (iters_limit < -1) return -13;
   if (!d_work) return -14;
   if (work_bytes < workspace_bytes()) return -15;
-  if (m > kPanelMaxWG * 1024) return -2;
+  if (m > kPanelMaxRows) return -2;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
   if (mn == 0) return 0;
-  if (zero_bytes(s, d_work, sizeof(GridBar)) != hipSuccess) return MLU_ERR_HIP;
+  if (zero_bytes(s, d_work, sizeof(PanelWork)) != hipSuccess) return MLU_ERR_HIP;
 
   std::vector<int> sched;
   int j = 0;
@@ -248,7 +249,8 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
     sched.push_back(b);
     j += b;
   }
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, reinterpret_cast<PanelWork*>(d_work)};
+  unsigned epoch = 0;
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, reinterpret_cast<PanelWork*>(d_work), &epoch};
   c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
 
   hipError_t e;
@@ -323,7 +325,7 @@ int mlu_dlaswp(void* stream, int m, int ncols, double* dA, int lda, int k1, int 
 
 int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info,
                      void* d_work, size_t work_bytes) {
-  if (m < 0 || m > kPanelMaxWG * 1024) return -2;
+  if (m < 0 || m > kPanelMaxRows) return -2;
   if (bw < 0 || bw > MLU_MAX_NB_INNER || bw > m) return -3;
   if (bw > 0 && !dA) return -4;
   if (lda < (bw > 1 ? bw : 1)) return -5;
@@ -334,10 +336,23 @@ int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
   if (bw == 0) return 0;
-  if (zero_bytes(s, d_work, sizeof(GridBar)) != hipSuccess) return MLU_ERR_HIP;
-  return panel_factor(s, dA, lda, m, bw, 0, d_ipiv, d_info, reinterpret_cast<PanelWork*>(d_work)) == hipSuccess
+  if (zero_bytes(s, d_work, sizeof(PanelWork)) != hipSuccess) return MLU_ERR_HIP;
+  return panel_factor(s, dA, lda, m, bw, 0, d_ipiv, d_info, reinterpret_cast<PanelWork*>(d_work), 1u) == hipSuccess
              ? 0
              : MLU_ERR_HIP;
+}
+
+int mlu_trace_begin(int capacity) {
+  if (capacity < 1 || capacity > (1 << 20)) return -1;
+  return trace_begin(capacity) == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+int mlu_trace_end(int* launches, double* total_ms, double* flops, double* bytes) {
+  if (!launches) return -1;
+  if (!total_ms) return -2;
+  if (!flops) return -3;
+  if (!bytes) return -4;
+  return trace_end(launches, total_ms, flops, bytes) == hipSuccess ? 0 : MLU_ERR_HIP;
 }
 
 }  // extern "C"

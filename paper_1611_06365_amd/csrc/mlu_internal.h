@@ -11,34 +11,35 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kWave = 64;
 
 // ---------------------------------------------------------------- panel kernel
-// Widest register-resident panel block and the largest number of cooperating
-// workgroups of one panel launch.
-constexpr int kPanelMaxCols = 32;
-constexpr int kPanelThreads = 256;
-constexpr int kPanelMaxWG = 128;
+// Widest register-resident panel block, the largest number of cooperating
+// workgroups of one panel launch and the tallest panel they hold (the leader
+// holds 512 rows, every other workgroup 1024).
+constexpr int kPanelMaxCols = 32;   // exchange-area width
+constexpr int kPanelRegCols = 16;   // widest block the kernel holds in registers
+constexpr int kPanelMaxWG = 33;
+constexpr int kPanelMaxRows = 512 + (kPanelMaxWG - 1) * 1024;
 
-// Cross-workgroup barrier state (device memory, zero at the start of a call).
-struct alignas(64) GridBar {
-  unsigned count;
-  unsigned gen;
-  unsigned err;
-  unsigned pad[13];
+// One published value: {value, aux, tag}, written and read as one 16-byte
+// device-coherent access so that the tag and the value arrive together.
+struct alignas(16) Chunk {
+  double v;
+  unsigned aux;
+  unsigned tag;
 };
 
-// One candidate published by a workgroup for the pivot of a column:
-// |value|, the relative row, the origin label of the row's contents and the
-// row's values in the block's columns.
-struct PanelSlot {
-  double absval;
-  long long row;
-  long long pad;
-  double vals[kPanelMaxCols];
-};
-
+// Cross-workgroup exchange area of the panel kernel.  Exact mode: per
+// workgroup a header {|candidate|, row} and the candidate row, plus the
+// diagonal row from workgroup 0, double-buffered by column parity.
+// Speculative mode: the leader's pivot row of every column, and each
+// workgroup's check result.  spec_off turns speculation off for the rest of a
+// call once it has failed.
 struct PanelWork {
-  GridBar bar;
-  PanelSlot slot[2][kPanelMaxWG];
-  PanelSlot diag[2];
+  Chunk hdr[2][kPanelMaxWG];
+  Chunk cand[2][kPanelMaxWG][kPanelMaxCols];
+  Chunk diag[2][kPanelMaxCols];
+  Chunk spec[kPanelMaxCols][kPanelMaxCols];
+  Chunk verify[kPanelMaxWG];
+  alignas(64) unsigned spec_off;
 };
 
 size_t workspace_bytes();
@@ -46,16 +47,22 @@ size_t workspace_bytes();
 // ---------------------------------------------------------------- launchers
 // All take row-major operands; element (i, j) of X is X[i*ldx + j].
 
-// C := C - A B   (A m x k, B k x n, C m x n)
+// C := C - A B   (A m x k, B k x n, C m x n).  `trailing` marks the outer
+// trailing updates (RL3, PF2, RU2): same kernel body, own kernel name, and
+// event-timed while a trace is active.
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda,
-                       const double* B, int ldb, double* C, int ldc);
+                       const double* B, int ldb, double* C, int ldc, bool trailing = false);
+hipError_t trace_begin(int capacity);
+hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 
 // Factor the m x bw block whose top-left entry is global diagonal entry
 // (row0, row0): partial pivoting over its rows, interchanges applied inside the
 // block only; ipiv[row0 + c] = row0 + p + 1 (1-based); a zero pivot sets
 // *info = row0 + c + 1 if *info was 0.
+// `epoch` must differ between the launches of one call (the exchange area is
+// cleared at the start of the call).
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0,
-                        int32_t* ipiv, int32_t* info, PanelWork* work);
+                        int32_t* ipiv, int32_t* info, PanelWork* work, unsigned epoch);
 
 // Apply interchanges ipiv[k1 .. k2) (1-based values, each >= its own index and
 // < m) to columns [ca0, ca1) and [cb0, cb1) of the m-row matrix A.

@@ -1,73 +1,69 @@
 // Panel factorization with partial pivoting (LU_unb of Fig. "LU", left, applied
-// to a block of at most 32 columns: the diagonal-block step RL1 / PF3 / LL3).
+// to a block of at most 16 columns: the diagonal-block step RL1 / PF3 / LL3).
 //
-// The m x bw block is held in registers across nwg cooperating workgroups of
-// 512 threads; thread t of workgroup w owns rows w*1024 + t + 512*k (k < R).
-// Per column c:
-//   1. each thread finds its best candidate |a(r, c)|, r >= c (first row on
-//      ties); a wave64 shuffle reduction and an LDS pass give the workgroup's;
-//   2. with nwg > 1, every workgroup publishes its candidate (value, row and the
-//      row's bw values) and workgroup 0 also publishes row c; one grid barrier;
-//      every wave then reduces the published candidates itself;
+// The m x bw block is held in registers by nwg cooperating workgroups
+// ("workers") of 512 threads.  Worker 0 (the leader) holds rows 0..511, one per
+// thread; worker w >= 1 holds rows 512 + (w-1)*1024 + t + 512*k (thread t,
+// k = 0, 1).  Rows 0..bw-1 (the diagonal rows) therefore always live in the
+// leader.
+//
+// Per column c (exact mode):
+//   1. each thread takes its best candidate |a(r, c)|, r >= c (first row on
+//      ties); a DPP wave reduction gives the wave's, whose owner lane copies its
+//      row into LDS; one workgroup barrier; every thread reduces the per-wave
+//      results to the worker's;
+//   2. with nwg > 1 the workers exchange candidates through device memory
+//      (below); one more barrier hands the winner to every thread;
 //   3. rows c and p are exchanged (inside the block only), a21 := a21 / alpha11
-//      (a true division, zero pivots skipped and reported), and the rank-1
+//      (a true division; a zero pivot is skipped and reported), and the rank-1
 //      update a22 := a22 - a21 a12^T runs on the owned rows.
-// One grid barrier per column is the whole cross-workgroup cost; the barrier is
-// a generation counter in device memory with agent-scope acquire/release and a
-// bounded wait (a timeout flags the call instead of hanging).
+//
+// Speculative mode (nwg > 1): the leader chooses each pivot among its own rows
+// and streams the pivot rows one way; the other workers apply them without
+// waiting for one another and check that none of their rows beats the chosen
+// pivot (their rows all come after the leader's, so a tie keeps the leader's
+// row, exactly as the first-row rule does).  One exchange at the end combines
+// the checks.  If every check held, the factorization IS the partial pivoting
+// one and is kept; otherwise the block, still untouched in global memory, is
+// reloaded and factored again in exact mode, and the rest of the call runs in
+// exact mode.  The result never depends on which path ran.
+//
+// Registers and code size: the column loop is rolled over groups of U columns.
+// Within a group the column index is a compile-time offset u; after each group
+// every register row is rotated left by U, so the current column always sits at
+// index u; LDS and exchanged rows use the same rotated frame and a final
+// rotation restores the order.
+//
+// Exchange protocol, with no fence and no atomic: every published value travels
+// in a 16-byte chunk {value, aux, tag} written by one device-coherent (sc1)
+// buffer_store_dwordx4, so value and tag land together; readers poll with sc1
+// loads until every tag they need matches.  The tag holds the launch epoch
+// (unique per launch within a call, the area being cleared at the start of the
+// call) and the column.  Exact-mode chunks are double-buffered by column
+// parity: a worker writes column c+2 only after reading every worker's column
+// c+1 chunk, which each wrote after finishing column c.  Speculative pivot rows
+// get one slot per column.  Publishing and polling are done by different waves
+// (a wave's loads would otherwise also wait for its own stores).  Every wait is
+// bounded: a timeout reports MLU_INFO_SYNC_TIMEOUT, never a hang.
 #include "mlu_internal.h"
 
 #include <climits>
+#include <cstddef>
 #include <type_traits>
 #include <utility>
 
 namespace mlu {
 namespace {
 
-constexpr int PT = 1024;  // rows per workgroup at R = 2
 constexpr int NT = 512;   // threads per workgroup
 constexpr int NWAVE = NT / kWave;
-constexpr long long kSpinLimit = 1LL << 22;  // ~0.1 s of s_sleep(1) polls
+constexpr int U = 4;      // columns per rolled step
+constexpr long long kSpinLimit = 1LL << 21;
+constexpr int kRowNone = INT_MAX;
+constexpr int kSc1 = 16;  // buffer cache policy: device-coherent
+constexpr unsigned kTagVerify = 62u;
 
-__device__ __forceinline__ void st_relaxed(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_relaxed(const double* p) {
-  unsigned long long x = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)x);
-}
-__device__ __forceinline__ void st_relaxed_i(long long* p, long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ long long ld_relaxed_i(const long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Barrier over the nwg co-resident workgroups of this launch.
-__device__ void grid_barrier(GridBar* bar, unsigned nwg, int32_t* info) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nwg - 1) {
-      __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(&bar->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          atomicExch(info, -999);
-          break;
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
@@ -78,211 +74,478 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-__device__ __forceinline__ bool better(double av, long long ar, double bv, long long br) {
-  return av > bv || (av == bv && ar < br);
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_max_step(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return dmax(v, __hiloint2double(hi, lo));
 }
 
-template <int BW, int R>
-__global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
-                                              int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
-                                              PanelWork* __restrict__ work, int nwg) {
-  __shared__ double s_val[NWAVE];
-  __shared__ long long s_row[NWAVE];
-  __shared__ double s_prow[BW];
-  __shared__ double s_drow[BW];
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wg = blockIdx.x;
-  const int base = wg * NT * R;
+// (max |value|, first row among the maxima) over the 64 lanes; the result is
+// wave-uniform.  Values are >= -1 (-1 marks "no candidate").
+__device__ __forceinline__ void wave_argmax(double& v, int& r) {
+  double w = v;
+  w = dpp_max_step<0xB1>(w);    // quad_perm [1,0,3,2]: lane ^ 1
+  w = dpp_max_step<0x4E>(w);    // quad_perm [2,3,0,1]: lane ^ 2
+  w = dpp_max_step<0x141>(w);   // row_half_mirror: the other quad of 8
+  w = dpp_max_step<0x140>(w);   // row_mirror: the other half of 16
+  w = dmax(dmax(readlane_f64(w, 0), readlane_f64(w, 16)), dmax(readlane_f64(w, 32), readlane_f64(w, 48)));
+  const unsigned long long tie = __ballot(v == w);
+  int rr;
+  if (__popcll(tie) == 1) {
+    rr = __builtin_amdgcn_readlane(r, __ffsll((long long)tie) - 1);
+  } else {   // several lanes hold the maximum: the smallest row wins
+    int x = (v == w) ? r : kRowNone;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off));
+    rr = x;
+  }
+  v = w;
+  r = rr;
+}
 
-  double v[R][BW];
-  int rows[R];
+__device__ __forceinline__ int wave_min_int(int x) {
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    rows[k] = base + tid + k * NT;
-    const bool ok = rows[k] < m;
-    const double* src = A + (size_t)(ok ? rows[k] : 0) * lda;
+  for (int off = 32; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off));
+  return x;
+}
+
+template <int BW>
+__device__ __forceinline__ void lds_put_row(double* dst, const double (&src)[BW]) {
 #pragma unroll
-    for (int c = 0; c < BW; ++c) v[k][c] = (ok && c < bw) ? src[c] : 0.0;
+  for (int j = 0; j < BW; j += 2) *reinterpret_cast<double2*>(dst + j) = make_double2(src[j], src[j + 1]);
+}
+template <int BW>
+__device__ __forceinline__ void lds_get_row(double (&dst)[BW], const double* src) {
+#pragma unroll
+  for (int j = 0; j < BW; j += 2) {
+    const double2 x = *reinterpret_cast<const double2*>(src + j);
+    dst[j] = x.x;
+    dst[j + 1] = x.y;
+  }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ void put_chunk(__amdgpu_buffer_rsrc_t rs, unsigned off, double v, unsigned aux,
+                                          unsigned tag) {
+  v4i x;
+  x[0] = __double2loint(v);
+  x[1] = __double2hiint(v);
+  x[2] = (int)aux;
+  x[3] = (int)tag;
+  __builtin_amdgcn_raw_buffer_store_b128(x, rs, (int)off, 0, kSc1);
+}
+__device__ __forceinline__ v4i get_chunk(__amdgpu_buffer_rsrc_t rs, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSc1);
+}
+__device__ __forceinline__ double chunk_val(v4i x) { return __hiloint2double(x[1], x[0]); }
+
+constexpr unsigned off_hdr(int par, int w) {
+  return (unsigned)offsetof(PanelWork, hdr) + (unsigned)((par * kPanelMaxWG + w) * 16);
+}
+constexpr unsigned off_cand(int par, int w, int t) {
+  return (unsigned)offsetof(PanelWork, cand) + (unsigned)(((par * kPanelMaxWG + w) * kPanelMaxCols + t) * 16);
+}
+constexpr unsigned off_diag(int par, int t) {
+  return (unsigned)offsetof(PanelWork, diag) + (unsigned)((par * kPanelMaxCols + t) * 16);
+}
+constexpr unsigned off_spec(int c, int t) {
+  return (unsigned)offsetof(PanelWork, spec) + (unsigned)((c * kPanelMaxCols + t) * 16);
+}
+constexpr unsigned off_verify(int w) { return (unsigned)offsetof(PanelWork, verify) + (unsigned)(w * 16); }
+
+// worker that holds a given row (rows as laid out above)
+__device__ __forceinline__ int worker_of(int r) { return r < NT ? 0 : 1 + (r - NT) / (2 * NT); }
+
+struct PanelShared {
+  double val[2][NWAVE];
+  int row[2][NWAVE];
+  int p[2];
+  int fail[NWAVE];
+  int gfail;
+  int zero_col;
+  int piv[kPanelMaxCols];
+};
+
+// Bounded poll of n chunks (lane i of the calling wave reads offs[i]) until all
+// tags match; returns the chunks.  Lanes may repeat offsets.
+template <int K>
+__device__ __forceinline__ void poll_chunks(__amdgpu_buffer_rsrc_t rs, const unsigned (&offs)[K], v4i (&out)[K],
+                                            unsigned tag, int lane, int32_t* info) {
+  long long spins = 0;
+  while (true) {
+    __asm__ volatile("" ::: "memory");   // the polled chunks change under us: reload on every pass
+#pragma unroll
+    for (int i = 0; i < K; ++i) out[i] = get_chunk(rs, offs[i]);
+    unsigned bad = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) bad |= (unsigned)out[i][3] ^ tag;
+    if (__all(bad == 0u)) return;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      if (lane == 0) atomicExch(info, -999);
+      return;
+    }
+  }
+}
+
+template <int BW, int MAXW>
+struct Panel {
+  static constexpr int kPoll = (MAXW * BW + kWave - 1) / kWave;   // candidate chunks per lane
+
+  double* A;
+  int lda, m, bw;
+  int32_t* info;
+  int nwg, wg, tid, lane, wave;
+  unsigned epoch;
+  __amdgpu_buffer_rsrc_t rs;
+  double (*s_cand)[NWAVE][BW];
+  double (*s_drow)[BW];
+  double (*s_prow)[BW];
+  double (*s_wrow)[BW];
+  PanelShared* sh;
+  double v[2][BW];
+  int rows[2];
+
+  __device__ __forceinline__ void load() {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const bool ok = rows[k] < m;
+      const double* src = A + (size_t)(ok ? rows[k] : 0) * lda;
+#pragma unroll
+      for (int c = 0; c < BW; ++c) v[k][c] = (ok && c < bw) ? src[c] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void store() {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (rows[k] < m) {
+        double* dst = A + (size_t)rows[k] * lda;
+#pragma unroll
+        for (int c = 0; c < BW; ++c)
+          if (c < bw) dst[c] = v[k][c];
+      }
+  }
+  __device__ __forceinline__ void rotate() {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      double t[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) t[j] = v[k][j];
+#pragma unroll
+      for (int j = 0; j < BW - U; ++j) v[k][j] = v[k][j + U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) v[k][BW - U + j] = t[j];
+    }
+  }
+  // after the groups that covered bw columns, finish the cycle of rotations
+  __device__ __forceinline__ void unrotate() {
+    for (int g = (bw + U - 1) / U; g < BW / U; ++g) rotate();
   }
 
-  // Columns are visited through a compile-time index so that v[k][c] stays in
-  // registers (a runtime column index would send the array to scratch).
-  static_for<BW>([&](auto cidx) {
-    constexpr int c = decltype(cidx)::value;
-    if (c < bw) {
-    // 1. candidate of this thread, wave and workgroup
-    double bv = -1.0;
-    long long br = LLONG_MAX;
+  // Steps 1 and the local reduction: this worker's best row and its values in
+  // LDS; returns (value, row, wave holding it).
+  template <int u, int par>
+  __device__ __forceinline__ void local_best(int c, double& bv, int& br, int& wbest) {
+    bv = -1.0;
+    br = kRowNone;
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < 2; ++k) {
       const int r = rows[k];
       if (r < m && r >= c) {
-        const double a = fabs(v[k][c]);
+        const double a = fabs(v[k][u]);
         if (a > bv) {
           bv = a;
           br = r;
         }
       }
     }
+    wave_argmax(bv, br);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const long long orr = __shfl_xor(br, off);
-      if (better(ov, orr, bv, br)) {
-        bv = ov;
-        br = orr;
-      }
+    for (int k = 0; k < 2; ++k) {
+      if (rows[k] == br) lds_put_row<BW>(s_cand[par][wave], v[k]);
+      if (rows[k] == c) lds_put_row<BW>(s_drow[par], v[k]);
     }
     if (lane == 0) {
-      s_val[wave] = bv;
-      s_row[wave] = br;
+      sh->val[par][wave] = bv;
+      sh->row[par][wave] = br;
     }
     __syncthreads();
-    bv = s_val[0];
-    br = s_row[0];
+    double wv[NWAVE];
+    int wr[NWAVE];
 #pragma unroll
-    for (int w = 1; w < NWAVE; ++w)
-      if (better(s_val[w], s_row[w], bv, br)) {
-        bv = s_val[w];
-        br = s_row[w];
-      }
-
-    long long p;
-    if (nwg > 1) {
-      PanelSlot* mine = &work->slot[c & 1][wg];
-      bool owner = false;
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-        if ((long long)rows[k] == br) {
-          owner = true;
-#pragma unroll
-          for (int cc = 0; cc < BW; ++cc) st_relaxed(&mine->vals[cc], v[k][cc]);
-        }
-      if (owner || (br == LLONG_MAX && tid == 0)) {
-        st_relaxed(&mine->absval, bv);
-        st_relaxed_i(&mine->row, br);
-        __threadfence();
-      }
-#pragma unroll
-      for (int k = 0; k < R; ++k)
-        if (rows[k] == c) {
-#pragma unroll
-          for (int cc = 0; cc < BW; ++cc) st_relaxed(&work->diag[c & 1].vals[cc], v[k][cc]);
-          __threadfence();
-        }
-      grid_barrier(&work->bar, (unsigned)nwg, info);
-      // every wave reduces the published candidates on its own
-      double gv = -1.0;
-      long long gr = LLONG_MAX;
-      int gw = 0;
-      for (int w = lane; w < nwg; w += kWave) {
-        const PanelSlot* sl = &work->slot[c & 1][w];
-        const double sv = ld_relaxed(&sl->absval);
-        const long long sr = ld_relaxed_i(&sl->row);
-        if (better(sv, sr, gv, gr)) {
-          gv = sv;
-          gr = sr;
-          gw = w;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(gv, off);
-        const long long orr = __shfl_xor(gr, off);
-        const int ow = __shfl_xor(gw, off);
-        if (better(ov, orr, gv, gr)) {
-          gv = ov;
-          gr = orr;
-          gw = ow;
-        }
-      }
-      p = gr;
-      if (tid < BW) {
-        s_prow[tid] = ld_relaxed(&work->slot[c & 1][gw].vals[tid]);
-        s_drow[tid] = ld_relaxed(&work->diag[c & 1].vals[tid]);
-      }
-    } else {
-      p = br;
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        if ((long long)rows[k] == p) {
-#pragma unroll
-          for (int cc = 0; cc < BW; ++cc) s_prow[cc] = v[k][cc];
-        }
-        if (rows[k] == c) {
-#pragma unroll
-          for (int cc = 0; cc < BW; ++cc) s_drow[cc] = v[k][cc];
-        }
-      }
+    for (int w = 0; w < NWAVE; ++w) {
+      wv[w] = sh->val[par][w];
+      wr[w] = sh->row[par][w];
     }
-    __syncthreads();
-
-    // 3. interchange rows c and p, scale, rank-1 update
-    const double piv = s_prow[c];
+    bv = wv[0];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
+    for (int w = 1; w < NWAVE; ++w) bv = dmax(bv, wv[w]);
+    wbest = 0;
+    br = kRowNone;
+#pragma unroll
+    for (int w = NWAVE - 1; w >= 0; --w)
+      if (wv[w] == bv && wr[w] <= br) {
+        br = wr[w];
+        wbest = w;
+      }
+  }
+
+  // Step 3 with the pivot row `prow` and the old diagonal row `drow` (LDS).
+  template <int u>
+  __device__ __forceinline__ void apply(int c, int lim, int p, const double* prow, const double* drow) {
+    const double piv = prow[u];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (rows[k] == c) lds_get_row<BW>(v[k], prow);
+      else if (rows[k] == p) lds_get_row<BW>(v[k], drow);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
       const int r = rows[k];
-      if (r == c) {
-#pragma unroll
-        for (int cc = 0; cc < BW; ++cc) v[k][cc] = s_prow[cc];
-      } else if ((long long)r == p) {
-#pragma unroll
-        for (int cc = 0; cc < BW; ++cc) v[k][cc] = s_drow[cc];
-      }
       if (r > c && r < m) {
-        double l = v[k][c];
+        double l = v[k][u];
         if (piv != 0.0) {
           l = l / piv;
-          v[k][c] = l;
+          v[k][u] = l;
         }
+        // entries past this column and inside the block; finished columns
+        // rotated to the end stay untouched
 #pragma unroll
-        for (int cc = c + 1; cc < BW; ++cc)
-          if (cc < bw) v[k][cc] = v[k][cc] - l * s_prow[cc];
+        for (int j = u + 1; j < BW; ++j) v[k][j] = v[k][j] - l * ((j < lim) ? prow[j] : 0.0);
       }
     }
-    if (wg == 0 && tid == 0) {
-      ipiv[c] = row0 + (int)p + 1;
-      if (piv == 0.0) atomicCAS(info, 0, row0 + c + 1);
+    if (tid == 0) {
+      sh->piv[c] = p;
+      if (piv == 0.0 && sh->zero_col < 0) sh->zero_col = c;
     }
-    }  // c < bw
-  });
+  }
 
+  // One full pass in exact mode.
+  __device__ __forceinline__ void exact_pass() {
+    for (int c0 = 0; c0 < bw; c0 += U) {
+      const int lim = bw - c0;
+      static_for<U>([&](auto uidx) {
+        constexpr int u = decltype(uidx)::value;
+        constexpr int par = u & 1;
+        const int c = c0 + u;
+        if (c < bw) {
+          double bv;
+          int br, wbest;
+          local_best<u, par>(c, bv, br, wbest);
+          int p = br;
+          const double* prow = s_cand[par][wbest];
+          if (nwg > 1) {
+            const unsigned tag = epoch * 64u + (unsigned)c;
+            if (wave == NWAVE - 1) {   // publish
+              if (lane < BW) put_chunk(rs, off_cand(par, wg, lane), s_cand[par][wbest][lane], 0u, tag);
+              if (wg == 0 && lane >= 32 && lane - 32 < BW)
+                put_chunk(rs, off_diag(par, lane - 32), s_drow[par][lane - 32], 0u, tag);
+              if (lane == 63) put_chunk(rs, off_hdr(par, wg), bv, (unsigned)br, tag);
+            } else if (wave == 0) {    // poll every worker's chunks of this column
+              unsigned offs[kPoll + 2];
+              v4i got[kPoll + 2];
+              offs[0] = off_hdr(par, min(lane, nwg - 1));
+              offs[1] = off_diag(par, lane % BW);
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    if (rows[k] < m) {
-      double* dst = A + (size_t)rows[k] * lda;
+              for (int i = 0; i < kPoll; ++i) {
+                const int f = min(lane + kWave * i, nwg * BW - 1);
+                offs[2 + i] = off_cand(par, f / BW, f % BW);
+              }
+              poll_chunks<kPoll + 2>(rs, offs, got, tag, lane, info);
+              double gv = lane < nwg ? chunk_val(got[0]) : -1.0;
+              int gr = lane < nwg ? got[0][2] : kRowNone;
+              wave_argmax(gv, gr);
+              const int gw = gr == kRowNone ? 0 : worker_of(gr);
+              if (lane == 0) sh->p[par] = gr;
 #pragma unroll
-      for (int c = 0; c < BW; ++c)
-        if (c < bw) dst[c] = v[k][c];
+              for (int i = 0; i < kPoll; ++i) {
+                const int f = lane + kWave * i;
+                if (f < nwg * BW && f / BW == gw) s_prow[par][f % BW] = chunk_val(got[2 + i]);
+              }
+              if (lane < BW) s_drow[par][lane] = chunk_val(got[1]);
+            }
+            __syncthreads();
+            p = sh->p[par];
+            prow = s_prow[par];
+          }
+          apply<u>(c, lim, p, prow, s_drow[par]);
+        }
+      });
+      rotate();
     }
+    unrotate();
+  }
+
+  // One pass in speculative mode; returns the first column at which one of this
+  // thread's rows beat the leader's pivot (bw if none).
+  __device__ __forceinline__ int spec_pass() {
+    int fail = bw;
+    for (int c0 = 0; c0 < bw; c0 += U) {
+      const int lim = bw - c0;
+      static_for<U>([&](auto uidx) {
+        constexpr int u = decltype(uidx)::value;
+        constexpr int par = u & 1;
+        const int c = c0 + u;
+        if (c < bw) {
+          const unsigned tag = epoch * 64u + (unsigned)c;
+          if (wg == 0) {
+            double bv;
+            int br, wbest;
+            local_best<u, par>(c, bv, br, wbest);
+            if (wave == NWAVE - 1 && lane < BW) put_chunk(rs, off_spec(c, lane), s_cand[par][wbest][lane], 0u, tag);
+            apply<u>(c, lim, br, s_cand[par][wbest], s_drow[par]);
+          } else {
+            // every wave fetches the pivot row on its own: no barrier
+            unsigned offs[1] = {off_spec(c, lane % BW)};
+            v4i got[1];
+            poll_chunks<1>(rs, offs, got, tag, lane, info);
+            // lane j holds entry j: stage the row in this wave's own LDS row
+            // (a wave's LDS accesses complete in order) and read it back
+            double* pr = s_wrow[wave];
+            if (lane < BW) pr[lane] = chunk_val(got[0]);
+            __builtin_amdgcn_wave_barrier();
+            const double piv = pr[u];
+            const double apiv = fabs(piv);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int r = rows[k];
+              if (r < m) {
+                if (fabs(v[k][u]) > apiv && fail > c) fail = c;
+                double l = v[k][u];
+                if (piv != 0.0) {
+                  l = l / piv;
+                  v[k][u] = l;
+                }
+#pragma unroll
+                for (int j = u + 1; j < BW; ++j) v[k][j] = v[k][j] - l * ((j < lim) ? pr[j] : 0.0);
+              }
+            }
+          }
+        }
+      });
+      rotate();
+    }
+    unrotate();
+    return fail;
+  }
+
+  // Combine the workers' checks: the first failing column over all workers.
+  __device__ __forceinline__ int verify(int fail) {
+    const int wf = wave_min_int(fail);
+    if (lane == 0) sh->fail[wave] = wf;
+    __syncthreads();
+    if (wave == 0) {
+      int f = sh->fail[0];
+#pragma unroll
+      for (int w = 1; w < NWAVE; ++w) f = min(f, sh->fail[w]);
+      const unsigned tag = epoch * 64u + kTagVerify;
+      if (lane == 0) put_chunk(rs, off_verify(wg), (double)f, 0u, tag);
+    } else if (wave == 1) {
+      unsigned offs[1] = {off_verify(min(lane, nwg - 1))};
+      v4i got[1];
+      poll_chunks<1>(rs, offs, got, epoch * 64u + kTagVerify, lane, info);
+      const int g = wave_min_int((int)chunk_val(got[0]));
+      if (lane == 0) sh->gfail = g;
+    }
+    __syncthreads();
+    return sh->gfail;
+  }
+};
+
+template <int BW, int MAXW>
+__global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
+                                              int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
+                                              PanelWork* __restrict__ work, int nwg, unsigned epoch) {
+  static_assert(BW % U == 0, "BW must be a multiple of U");
+  __shared__ __attribute__((aligned(16))) double s_cand[2][NWAVE][BW];
+  __shared__ __attribute__((aligned(16))) double s_drow[2][BW];
+  __shared__ __attribute__((aligned(16))) double s_prow[2][BW];
+  __shared__ __attribute__((aligned(16))) double s_wrow[NWAVE][BW];
+  __shared__ PanelShared sh;
+
+  Panel<BW, MAXW> P;
+  P.A = A;
+  P.lda = lda;
+  P.m = m;
+  P.bw = bw;
+  P.info = info;
+  P.nwg = nwg;
+  P.wg = blockIdx.x;
+  P.tid = threadIdx.x;
+  P.lane = threadIdx.x & 63;
+  P.wave = threadIdx.x >> 6;
+  P.epoch = epoch;
+  P.rs = rsrc_of(work);
+  P.s_cand = s_cand;
+  P.s_drow = s_drow;
+  P.s_prow = s_prow;
+  P.s_wrow = s_wrow;
+  P.sh = &sh;
+  if (P.wg == 0) {
+    P.rows[0] = P.tid;
+    P.rows[1] = kRowNone;
+  } else {
+    P.rows[0] = NT + (P.wg - 1) * 2 * NT + P.tid;
+    P.rows[1] = P.rows[0] + NT;
+  }
+  if (P.tid == 0) sh.zero_col = -1;
+  P.load();
+
+  bool done = false;
+  if (nwg > 1 && work->spec_off == 0u) {
+    const int fail = P.spec_pass();
+    if (P.verify(fail) >= bw) {
+      done = true;
+    } else {
+      if (P.wg == 0 && P.tid == 0) work->spec_off = 1u;
+      if (P.tid == 0) sh.zero_col = -1;
+      P.load();
+      __syncthreads();
+    }
+  }
+  if (!done) P.exact_pass();
+
+  P.store();
+  if (P.wg == 0) {
+    __syncthreads();
+    for (int c = P.tid; c < bw; c += NT) ipiv[c] = row0 + sh.piv[c] + 1;
+    if (P.tid == 0 && sh.zero_col >= 0) atomicCAS(info, 0, row0 + sh.zero_col + 1);
   }
 }
 
 template <int BW>
 hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work) {
-  if (m <= NT) {
-    hipLaunchKernelGGL((k_panel<BW, 1>), dim3(1), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, 1);
-  } else {
-    const int nwg = (m + PT - 1) / PT;
-    if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_panel<BW, 2>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work,
-                       nwg);
-  }
+                        int32_t* info, PanelWork* work, unsigned epoch) {
+  const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
+  if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
+  if (nwg <= 16)
+    hipLaunchKernelGGL((k_panel<BW, 16>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, nwg,
+                       epoch);
+  else
+    hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
+                       work, nwg, epoch);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work) {
+                        int32_t* info, PanelWork* work, unsigned epoch) {
   if (m <= 0 || bw <= 0) return hipSuccess;
-  if (bw > kPanelMaxCols || bw > m) return hipErrorInvalidValue;
+  if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows) return hipErrorInvalidValue;
   ipiv += row0;
-  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work);
-  if (bw <= 16) return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work);
-  return launch_panel<32>(s, A, lda, m, bw, row0, ipiv, info, work);
+  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch);
+  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch);
 }
 
 size_t workspace_bytes() { return (sizeof(PanelWork) + 4095) / 4096 * 4096; }

@@ -18,7 +18,7 @@ VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA}
 MLU_ERR_HIP = -1000
 MLU_INFO_SYNC_TIMEOUT = -999
 MLU_INFO_BAD_PIVOT = -998
-MLU_MAX_NB_INNER = 32
+MLU_MAX_NB_INNER = 16
 
 _vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
 
@@ -31,6 +31,9 @@ _SIGNATURES = {
     "mlu_dgemm_update": ([_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i], _i),
     "mlu_dlaswp": ([_vp, _i, _i, _vp, _i, _i, _i, _vp, _vp], _i),
     "mlu_dgetf2_block": ([_vp, _i, _i, _vp, _i, _vp, _vp, _vp, _sz], _i),
+    "mlu_trace_begin": ([_i], _i),
+    "mlu_trace_end": ([ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                       ctypes.POINTER(ctypes.c_double)], _i),
 }
 EXPORTED = tuple(_SIGNATURES)
 
@@ -95,6 +98,16 @@ def mlu_dlaswp(stream, m, ncols, dA, lda, k1, k2, d_ipiv, d_info) -> int:
 
 def mlu_dgetf2_block(stream, m, bw, dA, lda, d_ipiv, d_info, d_work, work_bytes) -> int:
     return _call("mlu_dgetf2_block", stream, m, bw, dA, lda, d_ipiv, d_info, d_work, work_bytes)
+
+
+def mlu_trace_begin(capacity) -> int:
+    return _call("mlu_trace_begin", capacity)
+
+
+def mlu_trace_end() -> tuple[int, int, float, float, float]:
+    n, ms, fl, by = _i(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    rc = _call("mlu_trace_end", ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by))
+    return rc, n.value, ms.value, fl.value, by.value
 
 
 # ---------------------------------------------------------------- torch marshalling

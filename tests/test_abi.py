@@ -31,7 +31,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("mlu_dgetrf", "mlu_dgetrf_workspace", "mlu_dtrsm", "mlu_dgetrs", "mlu_dgemm_update",
-                     "mlu_dlaswp", "mlu_dgetf2_block", "mlu_version"):
+                     "mlu_dlaswp", "mlu_dgetf2_block", "mlu_version", "mlu_trace_begin", "mlu_trace_end"):
         assert required in names
 
 
@@ -43,12 +43,12 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_version_and_workspace(lib):
     assert mlu.mlu_version() == 100
-    rc, nbytes = mlu.mlu_dgetrf_workspace(16384, 16384, mlu.MLU_LA, 256, 32)
+    rc, nbytes = mlu.mlu_dgetrf_workspace(16384, 16384, mlu.MLU_LA, 256, 16)
     assert rc == 0 and 0 < nbytes <= 1 << 20
     assert mlu.mlu_dgetrf_workspace(-1, 4, 0, 1, 0)[0] == -1
     assert mlu.mlu_dgetrf_workspace(4, 4, 7, 1, 0)[0] == -3
     assert mlu.mlu_dgetrf_workspace(4, 4, 0, 0, 0)[0] == -4
-    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 33)[0] == -5
+    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 17)[0] == -5
 
 
 def _getrf(**kw):
@@ -60,7 +60,7 @@ def _getrf(**kw):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(m=-1), -2), (dict(n=-3), -3), (dict(dA=None), -4), (dict(lda=7), -5), (dict(d_ipiv=None), -6),
-    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=33), -10),
+    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=17), -10),
     (dict(nb_inner=-1), -10), (dict(iters_limit=-2), -13), (dict(d_work=None), -14), (dict(work_bytes=16), -15),
 ])
 def test_getrf_argument_checks(lib, kw, code):
@@ -81,5 +81,5 @@ def test_other_argument_checks(lib):
     assert mlu.mlu_dgetrs(None, 4, 2, 1024, 3, 2048, 4096, 2) == -5
     assert mlu.mlu_dgemm_update(None, 4, 4, 4, 1024, 3, 2048, 4, 4096, 4) == -6
     assert mlu.mlu_dlaswp(None, 4, 4, 1024, 4, 2, 1, 2048, None) == -7
-    assert mlu.mlu_dgetf2_block(None, 8, 33, 1024, 33, 2048, 4096, 8192, 1 << 20) == -3
+    assert mlu.mlu_dgetf2_block(None, 32, 17, 1024, 17, 2048, 4096, 8192, 1 << 20) == -3
     assert mlu.mlu_dgetf2_block(None, 4, 8, 1024, 8, 2048, 4096, 8192, 1 << 20) == -3

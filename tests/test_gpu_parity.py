@@ -51,7 +51,7 @@ def gpu_getrf(A, variant, nb, nb_inner=0, schedule=None, iters_limit=-1):
 
 
 def inner_of(nb, nb_inner):
-    bi = nb_inner if nb_inner > 0 else min(nb, 32)
+    bi = nb_inner if nb_inner > 0 else min(nb, 16)
     return ("rl", bi)
 
 
@@ -92,7 +92,7 @@ def test_gemm_update_submatrix_strides():
 
 # ------------------------------------------------------------------ K1: panel kernel
 @pytest.mark.parametrize("m", [1, 5, 63, 300, 512, 513, 1024, 1025, 3000, 5000])
-@pytest.mark.parametrize("bw", [1, 7, 8, 16, 32])
+@pytest.mark.parametrize("bw", [1, 7, 8, 9, 16])
 def test_panel_block_uniform(m, bw):
     if bw > m:
         pytest.skip("bw > m")
@@ -108,7 +108,7 @@ def test_panel_block_uniform(m, bw):
     assert np.abs(F - R).max() <= 1e-13 * max(1.0, np.abs(R).max())
 
 
-@pytest.mark.parametrize("m,bw", [(40, 32), (2000, 32), (1500, 16), (4100, 8)])
+@pytest.mark.parametrize("m,bw", [(40, 16), (2000, 16), (1500, 16), (4100, 8), (17000, 16)])
 def test_panel_block_known_answer_exact(m, bw):
     A, perm, L, U = G.known_answer(m, bw, seed=m)
     dA = dev(A)
@@ -122,10 +122,10 @@ def test_panel_block_known_answer_exact(m, bw):
 
 
 def test_panel_block_ties_and_zero_pivot():
-    W = G.wilkinson_growth(32)
+    W = G.wilkinson_growth(16)
     dW = dev(W)
     ipiv, info = mlu.getf2_block(dW)
-    assert (host(ipiv)[:32] - 1).tolist() == list(range(32))
+    assert (host(ipiv)[:16] - 1).tolist() == list(range(16))
     R = W.copy()
     O.lu_unb(R)
     assert np.array_equal(host(dW), R)
@@ -140,6 +140,27 @@ def test_panel_block_ties_and_zero_pivot():
     assert int(host(info)[0]) == 1 == inf_[0]
     assert (host(ipiv)[:8] - 1).tolist() == opiv
     assert np.abs(host(dZ) - R).max() <= 1e-13
+
+
+@pytest.mark.parametrize("m,bw,fail_at", [(3000, 16, None), (3000, 16, 0), (3000, 16, 6), (5000, 8, 7),
+                                           (1000, 16, None), (17000, 16, 11)])
+def test_panel_block_speculation_paths(m, bw, fail_at):
+    # Tall blocks are first factored speculatively with pivots from the first
+    # 512 rows; pivot rows placed below them make that guess fail at column
+    # `fail_at` and the block is redone exactly.  Every path must give the
+    # partial-pivoting factorization, bit for bit on this exact input.
+    perm = G.leader_perm(m, bw, 512, fail_at, seed=m + bw)
+    A, perm, L, U = G.known_answer(m, bw, seed=m, perm=perm)
+    dA = dev(A)
+    ipiv, info = mlu.getf2_block(dA)
+    F = host(dA)
+    piv = (host(ipiv)[:bw] - 1).tolist()
+    R = A.copy()
+    opiv = O.lu_unb(R)
+    assert int(host(info)[0]) == 0
+    assert piv == opiv
+    assert np.array_equal(F, R)
+    assert np.array_equal(O.permutation_of(piv, m)[:bw], perm[:bw])
 
 
 # ------------------------------------------------------------------ K2: interchanges
@@ -340,6 +361,17 @@ def test_getrf_variants_agree_moderate_n():
     assert res["rl"][1] == res["ll"][1] == res["la"][1]
     for v in ("ll", "la"):
         assert np.abs(res[v][0] - res["rl"][0]).max() <= 1e-11 * np.abs(res["rl"][0]).max()
+
+
+@pytest.mark.parametrize("variant", ["rl", "la"])
+def test_getrf_spd_moderate_n(variant):
+    # tall panels with no interchange: the speculative panel path is kept
+    A = G.spd_bbt(1500, seed=3)
+    F, piv, info = gpu_getrf(A, variant, 256, 16)
+    R = A.copy()
+    opiv, _ = O.getrf(R, "rl", nb=256, inner=("rl", 16))
+    assert info == 0 and piv == opiv == list(range(1500))
+    assert np.abs(F - R).max() <= 1e-12 * np.abs(R).max()
 
 
 def test_getrs_solves():
