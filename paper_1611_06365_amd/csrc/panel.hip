@@ -18,11 +18,11 @@
 //      (a true division; a zero pivot is skipped and reported), and the rank-1
 //      update a22 := a22 - a21 a12^T runs on the owned rows.
 //
-// Speculative mode (nwg > 1): the leader chooses each pivot among its own rows
-// and streams the pivot rows one way; the other workers apply them without
-// waiting for one another and check that none of their rows beats the chosen
-// pivot (their rows all come after the leader's, so a tie keeps the leader's
-// row, exactly as the first-row rule does).  One exchange at the end combines
+// Speculative mode (m > 64): one wave, the leader (rows 0..63), chooses each
+// pivot among its own rows and streams the pivot rows one way; every other wave
+// applies them without waiting for any other wave and checks that none of its
+// rows beats the chosen pivot (its rows all come after the leader's, so a tie
+// keeps the leader's row, exactly as the first-row rule does).  One exchange at the end combines
 // the checks.  If every check held, the factorization IS the partial pivoting
 // one and is kept; otherwise the block, still untouched in global memory, is
 // reloaded and factored again in exact mode, and the rest of the call runs in
@@ -212,6 +212,8 @@ struct Panel {
   double (*s_drow)[BW];
   double (*s_prow)[BW];
   double (*s_wrow)[BW];
+  double (*s_lrow)[BW];
+  double (*s_ldrow)[BW];
   PanelShared* sh;
   double v[2][BW];
   int rows[2];
@@ -387,32 +389,72 @@ struct Panel {
   }
 
   // One pass in speculative mode; returns the first column at which one of this
-  // thread's rows beat the leader's pivot (bw if none).
+  // thread's rows beat the leader's pivot (bw if none).  The leader is wave 0
+  // of worker 0 (rows 0..63): it picks each pivot among its own rows with wave
+  // operations only and publishes the pivot row.  Every other wave follows on
+  // its own, with no barrier: it fetches the pivot rows of a whole group of U
+  // columns at once (one memory round trip when the leader is ahead), checks
+  // and updates its rows.
   __device__ __forceinline__ int spec_pass() {
     int fail = bw;
+    const bool leader = (wg == 0 && wave == 0);
     for (int c0 = 0; c0 < bw; c0 += U) {
       const int lim = bw - c0;
+      v4i cache[U];
       static_for<U>([&](auto uidx) {
         constexpr int u = decltype(uidx)::value;
         constexpr int par = u & 1;
         const int c = c0 + u;
         if (c < bw) {
           const unsigned tag = epoch * 64u + (unsigned)c;
-          if (wg == 0) {
-            double bv;
-            int br, wbest;
-            local_best<u, par>(c, bv, br, wbest);
-            if (wave == NWAVE - 1 && lane < BW) put_chunk(rs, off_spec(c, lane), s_cand[par][wbest][lane], 0u, tag);
-            apply<u>(c, lim, br, s_cand[par][wbest], s_drow[par]);
+          if (leader) {
+            const bool act = rows[0] < m && rows[0] >= c;
+            double bv = act ? fabs(v[0][u]) : -1.0;
+            int br = act ? rows[0] : kRowNone;
+            wave_argmax(bv, br);
+            const int p = br;
+            double* lp = s_lrow[par];
+            double* ld = s_ldrow[par];
+            if (rows[0] == p) lds_put_row<BW>(lp, v[0]);
+            if (rows[0] == c) lds_put_row<BW>(ld, v[0]);
+            __builtin_amdgcn_wave_barrier();   // a wave's LDS accesses complete in order
+            if (lane < BW) put_chunk(rs, off_spec(c, lane), lp[lane], 0u, tag);
+            const double piv = lp[u];
+            if (rows[0] == c) lds_get_row<BW>(v[0], lp);
+            else if (rows[0] == p) lds_get_row<BW>(v[0], ld);
+            if (rows[0] > c && rows[0] < m) {
+              double l = v[0][u];
+              if (piv != 0.0) {
+                l = l / piv;
+                v[0][u] = l;
+              }
+#pragma unroll
+              for (int j = u + 1; j < BW; ++j) v[0][j] = v[0][j] - l * ((j < lim) ? lp[j] : 0.0);
+            }
+            if (lane == 0) {
+              sh->piv[c] = p;
+              if (piv == 0.0 && sh->zero_col < 0) sh->zero_col = c;
+            }
           } else {
-            // every wave fetches the pivot row on its own: no barrier
-            unsigned offs[1] = {off_spec(c, lane % BW)};
-            v4i got[1];
-            poll_chunks<1>(rs, offs, got, tag, lane, info);
+            if (u == 0) {   // fetch the whole group's pivot rows in one go
+#pragma unroll
+              for (int i = 0; i < U; ++i) cache[i] = get_chunk(rs, off_spec(min(c0 + i, bw - 1), lane % BW));
+            }
+            long long spins = 0;
+            while (!__all((unsigned)cache[u][3] == tag)) {
+              __builtin_amdgcn_s_sleep(1);
+              __asm__ volatile("" ::: "memory");   // re-read the chunks not yet published
+#pragma unroll
+              for (int i = u; i < U; ++i) cache[i] = get_chunk(rs, off_spec(min(c0 + i, bw - 1), lane % BW));
+              if (++spins > kSpinLimit) {
+                if (lane == 0) atomicExch(info, -999);
+                break;
+              }
+            }
             // lane j holds entry j: stage the row in this wave's own LDS row
             // (a wave's LDS accesses complete in order) and read it back
             double* pr = s_wrow[wave];
-            if (lane < BW) pr[lane] = chunk_val(got[0]);
+            if (lane < BW) pr[lane] = chunk_val(cache[u]);
             __builtin_amdgcn_wave_barrier();
             const double piv = pr[u];
             const double apiv = fabs(piv);
@@ -471,6 +513,8 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   __shared__ __attribute__((aligned(16))) double s_drow[2][BW];
   __shared__ __attribute__((aligned(16))) double s_prow[2][BW];
   __shared__ __attribute__((aligned(16))) double s_wrow[NWAVE][BW];
+  __shared__ __attribute__((aligned(16))) double s_lrow[2][BW];
+  __shared__ __attribute__((aligned(16))) double s_ldrow[2][BW];
   __shared__ PanelShared sh;
 
   Panel<BW, MAXW> P;
@@ -490,6 +534,8 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   P.s_drow = s_drow;
   P.s_prow = s_prow;
   P.s_wrow = s_wrow;
+  P.s_lrow = s_lrow;
+  P.s_ldrow = s_ldrow;
   P.sh = &sh;
   if (P.wg == 0) {
     P.rows[0] = P.tid;
@@ -502,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   P.load();
 
   bool done = false;
-  if (nwg > 1 && work->spec_off == 0u) {
+  if (m > kWave && work->spec_off == 0u) {
     const int fail = P.spec_pass();
     if (P.verify(fail) >= bw) {
       done = true;

@@ -142,14 +142,14 @@ def test_panel_block_ties_and_zero_pivot():
     assert np.abs(host(dZ) - R).max() <= 1e-13
 
 
-@pytest.mark.parametrize("m,bw,fail_at", [(3000, 16, None), (3000, 16, 0), (3000, 16, 6), (5000, 8, 7),
+@pytest.mark.parametrize("m,bw,fail_at", [(3000, 16, None), (3000, 16, 0), (3000, 16, 6), (5000, 8, 7), (300, 16, None), (300, 16, 9),
                                            (1000, 16, None), (17000, 16, 11)])
 def test_panel_block_speculation_paths(m, bw, fail_at):
     # Tall blocks are first factored speculatively with pivots from the first
     # 512 rows; pivot rows placed below them make that guess fail at column
     # `fail_at` and the block is redone exactly.  Every path must give the
     # partial-pivoting factorization, bit for bit on this exact input.
-    perm = G.leader_perm(m, bw, 512, fail_at, seed=m + bw)
+    perm = G.leader_perm(m, bw, 64, fail_at, seed=m + bw)
     A, perm, L, U = G.known_answer(m, bw, seed=m, perm=perm)
     dA = dev(A)
     ipiv, info = mlu.getf2_block(dA)
