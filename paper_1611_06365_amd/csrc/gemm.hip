@@ -12,7 +12,11 @@
 //    source so global loads stay contiguous 64-byte runs per thread.
 //  * Inside a stage, MFMA step s (0..3) feeds lane group q = lane/16 with
 //    k = 4q + s.  A and B use the same k mapping, so every k is summed exactly
-//    once; lane (i, q) then reads its four A values as one 32-byte LDS run.
+//    once.  Each step's eight fragments are read from LDS one step ahead
+//    (two register sets), which keeps the kernel at 2 waves/SIMD unspilled.
+//  * The accumulators start as the C tile and B is negated as it is staged
+//    into LDS, so the MFMAs accumulate C - A B directly and the epilogue is a
+//    plain store: C is read once, ahead of the main loop, instead of after it.
 //  * Next stage's global loads are issued before the current stage's MFMAs.
 //  * Workgroup -> tile mapping is XCD-aware: hardware deals workgroups to the
 //    eight XCDs round-robin, so consecutive logical tiles are given to one XCD,
@@ -77,8 +81,8 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
         ra[2 * e] = x.x;
         ra[2 * e + 1] = x.y;
         double2 y = pb[e];
-        rb[2 * e] = y.x;
-        rb[2 * e + 1] = y.y;
+        rb[2 * e] = -y.x;
+        rb[2 * e + 1] = -y.y;
       }
     } else {
       const int gr = row0 + ar;
@@ -91,7 +95,7 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int gc = col0 + bc + e;
-        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+        rb[e] = (gk < k && gc < n) ? -B[(size_t)gk * ldb + gc] : 0.0;
       }
     }
   };
@@ -105,11 +109,19 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
     }
   };
 
+  // Accumulator layout of the 16x16 f64 block (measured on gfx950): lane
+  // (li, lq) holds rows lq + 4*r (r = 0..3) of column li.
   v4d acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
+        const int col = col0 + wn * 64 + j * 16 + li;
+        acc[i][j][r] = (interior_mn || (row < m && col < n)) ? C[(size_t)row * ldc + col] : 0.0;
+      }
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
@@ -120,34 +132,29 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
     const int buf = kt & 1;
     if (kt + 1 < nk) gload((kt + 1) * BK);
 
-    double a[4][4], b[4][4];
+    double a[2][4], b[2][4];
+    auto frag = [&](int st, int q) {
 #pragma unroll
-    for (int blk = 0; blk < 4; ++blk) {
-      const double* pa = &As[buf][(wm * 64 + blk * 16 + li) * LDS_A + 4 * lq];
-      const double2 a01 = *reinterpret_cast<const double2*>(pa);
-      const double2 a23 = *reinterpret_cast<const double2*>(pa + 2);
-      a[blk][0] = a01.x;
-      a[blk][1] = a01.y;
-      a[blk][2] = a23.x;
-      a[blk][3] = a23.y;
-      const double* pb = &Bs[buf][(4 * lq) * LDS_B + wn * 64 + blk * 16 + li];
+      for (int blk = 0; blk < 4; ++blk) {
+        a[q][blk] = As[buf][(wm * 64 + blk * 16 + li) * LDS_A + 4 * lq + st];
+        b[q][blk] = Bs[buf][(4 * lq + st) * LDS_B + wn * 64 + blk * 16 + li];
+      }
+    };
+    frag(0, 0);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) b[blk][s] = pb[s * LDS_B];
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int st = 0; st < 4; ++st) {
+      if (st + 1 < 4) frag(st + 1, (st + 1) & 1);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st & 1][i], b[st & 1][j], acc[i][j], 0, 0, 0);
+    }
 
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  // Accumulator layout of the 16x16 f64 block (measured on gfx950): lane
-  // (li, lq) holds rows lq + 4*r (r = 0..3) of column li.
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -156,10 +163,7 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
         const int col = col0 + wn * 64 + j * 16 + li;
-        if (row < m && col < n) {
-          double* pc = C + (size_t)row * ldc + col;
-          *pc = *pc - acc[i][j][r];
-        }
+        if (interior_mn || (row < m && col < n)) C[(size_t)row * ldc + col] = acc[i][j][r];
       }
 }
 
