@@ -112,7 +112,7 @@ def main() -> int:
     ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 1 GiB device copy (reference kernel for HBM counters)")
+                    help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -141,9 +141,10 @@ def main() -> int:
     torch.cuda.synchronize()
 
     if args.copy_calibration:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (x * 1.0)
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
