@@ -109,7 +109,7 @@ def main() -> int:
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--nb-inner", type=int, default=16)
     ap.add_argument("--matrix", default="spd", choices=["spd", "uniform"])
-    ap.add_argument("--cpu-n", type=int, default=4096, help="size of the CPU-oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=8192, help="size of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
