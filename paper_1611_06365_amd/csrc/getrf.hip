@@ -16,7 +16,7 @@
 //                              interchanges of the left columns
 //
 // The panel [A11; A21] is itself factored by the blocked RL algorithm with the
-// inner block size b_i <= 32, each b_i-wide block by the register-resident
+// inner block size b_i <= 16, each b_i-wide block by the register-resident
 // kernel (the paper's outer / inner LU, Section 4.2).
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
