@@ -35,11 +35,9 @@ constexpr int LDS_A = BK + 2;    // 144-byte row pitch: 16-byte reads of 8 lanes
 constexpr int LDS_B = BN + 4;    // row pitch offset so lane groups q, q+1 use different banks
 constexpr int GROUP_M = 8;
 
-__device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int T = tiles_m * tiles_n;
-  const int nfull = (T / 8) * 8;
-  int t = wg;
-  if (wg < nfull) t = (wg & 7) * (nfull >> 3) + (wg >> 3);
+// Logical tile t -> (tile row, tile column): tiles walk groups of GROUP_M tile
+// rows column by column, so neighbouring t share A rows and B columns.
+__device__ __forceinline__ void group_coords(int t, int tiles_m, int tiles_n, int& tm, int& tn) {
   const int per_group = GROUP_M * tiles_n;
   const int group = t / per_group;
   const int first_m = group * GROUP_M;
@@ -49,15 +47,29 @@ __device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, in
   tn = within / gsz;
 }
 
+// Workgroup -> tile for one-tile-per-workgroup launches: workgroups are dealt
+// to the XCDs round-robin, so XCD x (= wg mod 8) gets the contiguous logical
+// range starting at x * T/8.
+__device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int T = tiles_m * tiles_n;
+  const int nfull = (T / 8) * 8;
+  int t = wg;
+  if (wg < nfull) t = (wg & 7) * (nfull >> 3) + (wg >> 3);
+  group_coords(t, tiles_m, tiles_n, tm, tn);
+}
+
+__device__ __forceinline__ unsigned hw_xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 7u; }
+__device__ __forceinline__ unsigned hw_cu_id() { return (__builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11)) >> 8) & 15u; }
+
+// One 128 x 128 tile of C := C - A B.  Ends with a workgroup barrier, so the
+// caller may start another tile at once.
 template <bool VEC>
-__device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __restrict__ A, int lda,
-                                          const double* __restrict__ B, int ldb, double* __restrict__ C,
-                                          int ldc, int tiles_m, int tiles_n) {
+__device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                          int lda, const double* __restrict__ B, int ldb,
+                                          double* __restrict__ C, int ldc) {
   __shared__ double As[2][BM * LDS_A];
   __shared__ double Bs[2][BK * LDS_B];
 
-  int tm, tn;
-  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
   const int row0 = tm * BM, col0 = tn * BN;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -112,16 +124,26 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
   // Accumulator layout of the 16x16 f64 block (measured on gfx950): lane
   // (li, lq) holds rows lq + 4*r (r = 0..3) of column li.
   v4d acc[4][4];
+  double* const cbase = C + (size_t)(row0 + wm * 64 + lq) * ldc + col0 + wn * 64 + li;
+  if (interior_mn) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
-        const int col = col0 + wn * 64 + j * 16 + li;
-        acc[i][j][r] = (interior_mn || (row < m && col < n)) ? C[(size_t)row * ldc + col] : 0.0;
-      }
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
+          const int col = col0 + wn * 64 + j * 16 + li;
+          acc[i][j][r] = (row < m && col < n) ? cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] : 0.0;
+        }
+  }
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
@@ -155,16 +177,25 @@ __device__ __forceinline__ void gemm_body(int m, int n, int k, const double* __r
     __syncthreads();
   }
 
+  if (interior_mn) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
-        const int col = col0 + wn * 64 + j * 16 + li;
-        if (interior_mn || (row < m && col < n)) C[(size_t)row * ldc + col] = acc[i][j][r];
-      }
+        for (int r = 0; r < 4; ++r) cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] = acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + wm * 64 + i * 16 + lq + 4 * r;
+          const int col = col0 + wn * 64 + j * 16 + li;
+          if (row < m && col < n) cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] = acc[i][j][r];
+        }
+  }
 }
 
 // Generic launches (inner panel updates, blocked triangular solves) and the
@@ -175,14 +206,58 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(int m, int n, int k, con
                                                         int lda, const double* __restrict__ B, int ldb,
                                                         double* __restrict__ C, int ldc, int tiles_m,
                                                         int tiles_n) {
-  gemm_body<VEC>(m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 template <bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, const double* __restrict__ A,
                                                           int lda, const double* __restrict__ B, int ldb,
                                                           double* __restrict__ C, int ldc, int tiles_m,
                                                           int tiles_n) {
-  gemm_body<VEC>(m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
+// Persistent form for the look-ahead variant's RU2: queue x holds the logical
+// tiles [x T / 8, (x + 1) T / 8); a workgroup takes tickets from the queue of
+// the XCD it runs on, then from the other queues in turn, and leaves when all
+// are exhausted.  Tickets past a queue's end are harmless (the counters are
+// cleared before the slot is used again).  No workgroup waits for another, so
+// the launch drains whatever runs beside it.
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_queue(int m, int n, int k, const double* __restrict__ A,
+                                                       int lda, const double* __restrict__ B, int ldb,
+                                                       double* __restrict__ C, int ldc, int tiles_m,
+                                                       int tiles_n, unsigned* __restrict__ q,
+                                                       unsigned* __restrict__ clear, int reserve) {
+  __shared__ int s_t;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && clear != nullptr && tid < kXcd) clear[tid * kQueueStride] = 0u;
+  if (reserve > 0 && (int)(hw_cu_id() & 7u) < reserve) return;   // uniform over the workgroup
+  const long long T = (long long)tiles_m * tiles_n;
+  int x = (int)hw_xcc_id();
+  int empty = 0;
+  while (empty < kXcd) {
+    if (tid == 0) {
+      const long long lo = T * x / kXcd, hi = T * (x + 1) / kXcd;
+      const unsigned ticket = atomicAdd(&q[x * kQueueStride], 1u);
+      s_t = (lo + (long long)ticket < hi) ? (int)(lo + ticket) : -1;
+    }
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_t);
+    __syncthreads();
+    if (t < 0) {
+      ++empty;
+      x = (x + 1) & (kXcd - 1);
+      continue;
+    }
+    empty = 0;
+    int tm, tn;
+    group_coords(t, tiles_m, tiles_n, tm, tn);
+    gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  }
 }
 
 // Event timing of the outer trailing-update launches (see mlu_trace_begin).
@@ -195,6 +270,19 @@ struct Trace {
 };
 Trace g_trace;
 
+// The event pair for one traced launch of an m x n x k update (none once the
+// capacity is used up or no trace is active).
+void trace_slot(int m, int n, int k, hipEvent_t* e0, hipEvent_t* e1) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  if (g_trace.on && g_trace.used < g_trace.cap) {
+    *e0 = g_trace.ev[2 * g_trace.used];
+    *e1 = g_trace.ev[2 * g_trace.used + 1];
+    ++g_trace.used;
+    g_trace.flops += 2.0 * m * (double)n * k;
+    g_trace.bytes += 8.0 * (2.0 * m * (double)n + (double)m * k + (double)k * n);
+  }
+}
+
 }  // namespace
 
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
@@ -206,16 +294,7 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
   const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
                    (lda % 2 == 0) && (ldb % 2 == 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (trailing) {
-    std::lock_guard<std::mutex> lk(g_trace.mu);
-    if (g_trace.on && g_trace.used < g_trace.cap) {
-      e0 = g_trace.ev[2 * g_trace.used];
-      e1 = g_trace.ev[2 * g_trace.used + 1];
-      ++g_trace.used;
-      g_trace.flops += 2.0 * m * (double)n * k;
-      g_trace.bytes += 8.0 * (2.0 * m * (double)n + (double)m * k + (double)k * n);
-    }
-  }
+  if (trailing) trace_slot(m, n, k, &e0, &e1);
   if (e0) {
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
@@ -228,6 +307,46 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
     if (vec) hipLaunchKernelGGL(k_gemm_update<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
     else hipLaunchKernelGGL(k_gemm_update<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
   }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+  return e;
+}
+
+hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced) {
+  if (m <= 0 || n <= 0 || k <= 0) {
+    if (clear == nullptr) return hipSuccess;
+    m = n = k = 0;   // still clear the next slot
+  }
+  const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+  const long long tiles = (long long)tiles_m * tiles_n;
+  if (tiles > 0x7fffffffLL / kXcd) return hipErrorInvalidValue;
+  if (reserve < 0 || reserve >= 8) return hipErrorInvalidValue;
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
+                   (lda % 2 == 0) && (ldb % 2 == 0);
+  if (tiles == 0) {
+    grid = 1;
+    reserve = 0;
+  }
+  if (grid <= 0) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    grid = 2 * cus;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (traced && tiles > 0) trace_slot(m, n, k, &e0, &e1);
+  if (e0) {
+    hipError_t e = hipEventRecord(e0, s);
+    if (e != hipSuccess) return e;
+  }
+  if (vec)
+    hipLaunchKernelGGL(k_gemm_queue<true>, dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m,
+                       tiles_n, q, clear, reserve);
+  else
+    hipLaunchKernelGGL(k_gemm_queue<false>, dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc,
+                       tiles_m, tiles_n, q, clear, reserve);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
   return e;

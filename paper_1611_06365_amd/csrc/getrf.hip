@@ -36,8 +36,15 @@ __global__ void k_zero(unsigned* p, size_t nwords) {
 struct AuxStreams {
   bool ready = false;
   hipStream_t s1 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr;
 };
+
+// Look-ahead overlap: RU2 leaves the CUs with id < kLaReserve (mod 8) in every
+// shader engine (4 per XCD per unit, 32 per unit on the chip) to the panel
+// factorization, whose register-resident kernel needs whole CUs; once PF3 is
+// done, kLaHelpers workgroups on the panel's stream join RU2's tile queue.
+constexpr int kLaReserve = 1;
+constexpr int kLaHelpers = 64 * kLaReserve;
 std::mutex g_aux_mu;
 AuxStreams g_aux[64];
 
@@ -52,6 +59,7 @@ hipError_t get_aux(AuxStreams** out) {
     if ((e = hipStreamCreateWithFlags(&a.s1, hipStreamNonBlocking)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.ru1, hipEventDisableTiming)) != hipSuccess) return e;
     a.ready = true;
   }
   *out = &a;
@@ -71,6 +79,7 @@ struct Ctx {
   int32_t* info;
   int bi;
   PanelWork* work;
+  QueueWork* queue;
   unsigned* epoch;   // panel launch counter of this call (panels run one at a time)
   double* at(int i, int j) const { return A + (size_t)i * lda + j; }
 };
@@ -94,12 +103,12 @@ hipError_t factor_panel(hipStream_t s, const Ctx& c, int j, int b) {
 }
 
 // RL2 + RL3 (also RU1 + RU2 / PF1 + PF2) on columns [c0, c1) for the panel at j (size b)
-hipError_t update_cols(hipStream_t s, const Ctx& c, int j, int b, int c0, int c1) {
+hipError_t update_cols(hipStream_t s, const Ctx& c, int j, int b, int c0, int c1, bool traced = true) {
   if (c1 <= c0) return hipSuccess;
   MLU_TRY(trsm_left(s, true, true, b, c1 - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
   if (j + b < c.m)
     MLU_TRY(gemm_update(s, c.m - j - b, c1 - c0, b, c.at(j + b, j), c.lda, c.at(j, c0), c.lda, c.at(j + b, c0),
-                        c.lda, /*trailing=*/true));
+                        c.lda, traced));
   return hipSuccess;
 }
 
@@ -133,10 +142,24 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
     const int bp = (k + 1 < sched.size()) ? sched[k + 1] : 0;
     if (bp > 0) {
       MLU_TRY(hipEventRecord(aux->fork, s0));
+      // T_RU: RU1, then RU2 as a persistent tile queue that leaves CUs to T_PF
+      // (enqueued first, so that it is running while the host is still
+      // enqueueing the panel's many short launches)
+      const int c0 = jn + bp;
+      unsigned* q = c.queue->ctr[k % kQueueSlots];
+      unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
+      if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
+      MLU_TRY(hipEventRecord(aux->ru1, s0));
+      const int mr = c.m - jn, nr = c.n - c0;
+      MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
+                         kLaReserve, 0, true));
+      // T_PF: PF1, PF2, PF3, then it joins RU2's queue (after RU1 is done)
       MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
-      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp));                            // PF1, PF2
+      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));         // PF1, PF2
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
-      MLU_TRY(update_cols(s0, c, j, b, jn + bp, c.n));                           // RU1, RU2
+      MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
+      MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
+                         0, kLaHelpers, false));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
     } else {
@@ -166,7 +189,7 @@ hipError_t run_ll(hipStream_t s, const Ctx& c, const std::vector<int>& sched, in
       const int bl = sched[l];
       MLU_TRY(trsm_left(s, true, true, bl, b, c.at(jl, jl), c.lda, c.at(jl, j), c.lda));
       MLU_TRY(gemm_update(s, c.m - jl - bl, b, bl, c.at(jl + bl, jl), c.lda, c.at(jl, j), c.lda,
-                          c.at(jl + bl, j), c.lda));
+                          c.at(jl + bl, j), c.lda, /*trailing=*/true));
       jl += bl;
     }
     MLU_TRY(factor_panel(s, c, j, b));                                           // LL3
@@ -235,7 +258,7 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
   if (mn == 0) return 0;
-  if (zero_bytes(s, d_work, sizeof(PanelWork)) != hipSuccess) return MLU_ERR_HIP;
+  if (zero_bytes(s, d_work, sizeof(Workspace)) != hipSuccess) return MLU_ERR_HIP;
 
   std::vector<int> sched;
   int j = 0;
@@ -250,7 +273,8 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
     j += b;
   }
   unsigned epoch = 0;
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, reinterpret_cast<PanelWork*>(d_work), &epoch};
+  Workspace* ws = reinterpret_cast<Workspace*>(d_work);
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, &epoch};
   c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
 
   hipError_t e;
@@ -336,8 +360,8 @@ int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
   if (bw == 0) return 0;
-  if (zero_bytes(s, d_work, sizeof(PanelWork)) != hipSuccess) return MLU_ERR_HIP;
-  return panel_factor(s, dA, lda, m, bw, 0, d_ipiv, d_info, reinterpret_cast<PanelWork*>(d_work), 1u) == hipSuccess
+  if (zero_bytes(s, d_work, sizeof(Workspace)) != hipSuccess) return MLU_ERR_HIP;
+  return panel_factor(s, dA, lda, m, bw, 0, d_ipiv, d_info, &reinterpret_cast<Workspace*>(d_work)->panel, 1u) == hipSuccess
              ? 0
              : MLU_ERR_HIP;
 }

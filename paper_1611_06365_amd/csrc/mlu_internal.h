@@ -42,6 +42,22 @@ struct PanelWork {
   alignas(64) unsigned spec_off;
 };
 
+// Tile queues of the persistent trailing update (one per XCD, each counter on
+// its own 128-byte line), in a ring of slots: the update of look-ahead
+// iteration i takes slot i mod kQueueSlots and clears slot (i + 2) mod
+// kQueueSlots, whose last users finished before it started.
+constexpr int kXcd = 8;
+constexpr int kQueueStride = 32;   // unsigned words between counters
+constexpr int kQueueSlots = 4;
+struct QueueWork {
+  alignas(128) unsigned ctr[kQueueSlots][kXcd * kQueueStride];
+};
+
+struct Workspace {
+  PanelWork panel;
+  QueueWork queue;
+};
+
 size_t workspace_bytes();
 
 // ---------------------------------------------------------------- launchers
@@ -52,6 +68,17 @@ size_t workspace_bytes();
 // event-timed while a trace is active.
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda,
                        const double* B, int ldb, double* C, int ldc, bool trailing = false);
+// The same update as a persistent kernel fed by the tile queues of one slot
+// (`q`: kXcd counters kQueueStride words apart, zero before the first launch
+// that uses them).  Each workgroup takes tiles from the queue of its own XCD,
+// then from the others.  `reserve` > 0 makes workgroups that start on a CU
+// whose id within its shader engine is < reserve (mod 8) leave at once, so those
+// CUs stay free for the panel factorization running beside it; only valid when
+// another launch on the same queue without reserve follows (it finishes the
+// tiles).  `clear` (may be null): kXcd counters that workgroup 0 zeroes first.
+// `grid` 0 = two workgroups per CU.
+hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
+                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced);
 hipError_t trace_begin(int capacity);
 hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 

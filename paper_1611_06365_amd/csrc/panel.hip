@@ -594,6 +594,6 @@ hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int ro
   return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch);
 }
 
-size_t workspace_bytes() { return (sizeof(PanelWork) + 4095) / 4096 * 4096; }
+size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }
 
 }  // namespace mlu

@@ -4,61 +4,120 @@
 // the solve entry point also takes the upper / non-unit forms used by the
 // back substitution of a linear solve.
 //
-// A block of at most 32 rows is solved by one kernel in which each thread owns
-// one column of B in registers and reads T through uniform (scalar) loads.
-// Taller triangles are processed in 32-row blocks: solve a block, then update
-// the rows still to be solved with the matrix-core GEMM (C := C - A B).
+// One kernel solves a triangle of up to 256 rows.  Each workgroup owns a block
+// of 32 columns of B, which it keeps in LDS for the whole solve (read once,
+// written once), and runs blocked substitution on it: for each 16-row diagonal
+// block, 32 threads solve the block's rows (column by column, T's diagonal
+// block staged in LDS), then the four waves update the rows still to be solved
+// with v_mfma_f64_16x16x4f64 (A = -T from global memory, B = the solved rows,
+// C = the LDS rows).  Taller triangles are processed in 256-row blocks: solve a
+// block, then update the rows still to be solved with the matrix-core GEMM.
 #include "mlu_internal.h"
 
 namespace mlu {
 namespace {
 
-constexpr int kRows = 32;
+constexpr int kRows = 256;     // rows per kernel
+constexpr int kCols = 32;      // columns of B per workgroup
+constexpr int kPitch = kCols + 4;
+constexpr int kDiag = 16;      // diagonal block
 
 template <bool LOWER, bool UNIT>
-__global__ __launch_bounds__(256) void k_trsm_block(int nr, int ncols, const double* __restrict__ T, int ldt,
-                                                    double* __restrict__ B, int ldb) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  double x[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) x[r] = (r < nr) ? B[(size_t)r * ldb + col] : 0.0;
-  if (LOWER) {
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      if (r < nr) {
-        double s = x[r];
-#pragma unroll
-        for (int c = 0; c < r; ++c) s = s - T[(size_t)r * ldt + c] * x[c];
-        if (!UNIT) s = s / T[(size_t)r * ldt + r];
-        x[r] = s;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int r = kRows - 1; r >= 0; --r) {
-      if (r < nr) {
-        double s = x[r];
-#pragma unroll
-        for (int c = r + 1; c < kRows; ++c)
-          if (c < nr) s = s - T[(size_t)r * ldt + c] * x[c];
-        if (!UNIT) s = s / T[(size_t)r * ldt + r];
-        x[r] = s;
-      }
-    }
+__global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const double* __restrict__ T, int ldt,
+                                                  double* __restrict__ B, int ldb) {
+  __shared__ __attribute__((aligned(16))) double X[kRows * kPitch];
+  __shared__ double Td[kDiag][kDiag + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int c0 = blockIdx.x * kCols;
+
+  // B block -> LDS (rows >= nr and columns >= ncols are zero and never stored)
+  for (int e = tid; e < kRows * kCols; e += 256) {
+    const int r = e / kCols, c = e % kCols;
+    X[r * kPitch + c] = (r < nr && c0 + c < ncols) ? B[(size_t)r * ldb + c0 + c] : 0.0;
   }
+
+  const int nblk = (nr + kDiag - 1) / kDiag;
+  for (int step = 0; step < nblk; ++step) {
+    const int blk = LOWER ? step : nblk - 1 - step;
+    const int ib = blk * kDiag;
+    const int bs = min(kDiag, nr - ib);
+    // T's diagonal block -> LDS
+    {
+      const int r = tid / kDiag, c = tid % kDiag;
+      Td[r][c] = (r < bs && c < bs) ? T[(size_t)(ib + r) * ldt + ib + c] : 0.0;
+    }
+    __syncthreads();
+    // solve the block's rows, one column per thread
+    if (tid < kCols) {
+      double x[kDiag];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r)
-    if (r < nr) B[(size_t)r * ldb + col] = x[r];
+      for (int r = 0; r < kDiag; ++r) x[r] = X[(ib + r) * kPitch + tid];
+      if (LOWER) {
+#pragma unroll
+        for (int r = 0; r < kDiag; ++r) {
+          if (r < bs) {
+            double v = x[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q) v = v - Td[r][q] * x[q];
+            if (!UNIT) v = v / Td[r][r];
+            x[r] = v;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = kDiag - 1; r >= 0; --r) {
+          if (r < bs) {
+            double v = x[r];
+#pragma unroll
+            for (int q = r + 1; q < kDiag; ++q)
+              if (q < bs) v = v - Td[r][q] * x[q];
+            if (!UNIT) v = v / Td[r][r];
+            x[r] = v;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kDiag; ++r)
+        if (r < bs) X[(ib + r) * kPitch + tid] = x[r];
+    }
+    __syncthreads();
+    // rows still to be solved: below the block (lower) or above it (upper)
+    const int rlo = LOWER ? ib + kDiag : 0;
+    const int rhi = LOWER ? nr : ib;
+    const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
+    for (int item = wave; item < 2 * nrb; item += 4) {
+      const int R0 = rlo + (item >> 1) * 16, ch = (item & 1) * 16;
+      v4d acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = X[(R0 + lq + 4 * r) * kPitch + ch + li];
+      const int tr = R0 + li;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = 4 * lq + st;   // MFMA step st feeds lane group lq with k = 4 lq + st
+        const double a = (tr < nr && k < bs) ? -T[(size_t)tr * ldt + ib + k] : 0.0;
+        const double b = X[(ib + k) * kPitch + ch + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[(R0 + lq + 4 * r) * kPitch + ch + li] = acc[r];
+    }
+    __syncthreads();
+  }
+
+  for (int e = tid; e < kRows * kCols; e += 256) {
+    const int r = e / kCols, c = e % kCols;
+    if (r < nr && c0 + c < ncols) B[(size_t)r * ldb + c0 + c] = X[r * kPitch + c];
+  }
 }
 
 hipError_t solve_block(hipStream_t s, bool lower, bool unit, int nr, int ncols, const double* T, int ldt,
                        double* B, int ldb) {
-  const dim3 grid((ncols + 255) / 256), block(256);
-  if (lower && unit) hipLaunchKernelGGL((k_trsm_block<true, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else if (lower) hipLaunchKernelGGL((k_trsm_block<true, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else if (unit) hipLaunchKernelGGL((k_trsm_block<false, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else hipLaunchKernelGGL((k_trsm_block<false, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
+  const dim3 grid((ncols + kCols - 1) / kCols), block(256);
+  if (lower && unit) hipLaunchKernelGGL((k_trsm_lds<true, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
+  else if (lower) hipLaunchKernelGGL((k_trsm_lds<true, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
+  else if (unit) hipLaunchKernelGGL((k_trsm_lds<false, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
+  else hipLaunchKernelGGL((k_trsm_lds<false, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
   return hipGetLastError();
 }
 
