@@ -60,7 +60,7 @@ constexpr int NWAVE = NT / kWave;
 constexpr int U = 4;      // columns per rolled step
 constexpr long long kSpinLimit = 1LL << 21;
 constexpr int kRowNone = INT_MAX;
-constexpr int kSc1 = 16;  // buffer cache policy: device-coherent
+constexpr int kSc1 = 16;  // buffer cache policy of the publishing stores: device-coherent
 constexpr unsigned kTagVerify = 62u;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -76,11 +76,27 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 
+// Workgroup barrier that orders LDS only.  The waves exchange nothing through
+// global memory inside a workgroup, and a full barrier would also wait for the
+// wave's outstanding device-coherent stores (the vector memory counter counts
+// stores), a round trip of about a microsecond per column.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp_max_step(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return dmax(v, __hiloint2double(hi, lo));
+}
+
+// value of `v` in lane `src` (any lane, per lane)
+__device__ __forceinline__ double bpermute_f64(int src, double v) {
+  return __hiloint2double(__builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v)),
+                          __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v)));
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -144,9 +160,69 @@ __device__ __forceinline__ void put_chunk(__amdgpu_buffer_rsrc_t rs, unsigned of
   x[3] = (int)tag;
   __builtin_amdgcn_raw_buffer_store_b128(x, rs, (int)off, 0, kSc1);
 }
-__device__ __forceinline__ v4i get_chunk(__amdgpu_buffer_rsrc_t rs, unsigned off) {
-  return __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kSc1);
+// Polled reads of chunks: device-coherent (sc1) 16-byte loads written as one
+// volatile asm block that issues them all and waits for them all, so that a
+// wait loop really reads memory again on every pass (the compiler may
+// otherwise keep a load's value from an earlier pass) and every load has
+// landed before its registers are used.  Lane-wise, chunk i is read at
+// base + offs[i]; unused slots of a block repeat the last address.
+template <int K>
+__device__ __forceinline__ void get_chunks(const char* base, const unsigned (&offs)[K], v4i (&out)[K]) {
+  static_assert(K >= 1 && K <= 12, "at most 12 chunks per poll");
+  const v4i* p[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) p[i] = reinterpret_cast<const v4i*>(base + offs[i < K ? i : K - 1]);
+  v4i r[12];
+  if constexpr (K <= 4) {
+    asm volatile(
+        "global_load_dwordx4 %0, %4, off sc1\n\t"
+        "global_load_dwordx4 %1, %5, off sc1\n\t"
+        "global_load_dwordx4 %2, %6, off sc1\n\t"
+        "global_load_dwordx4 %3, %7, off sc1\n\t"
+        "s_waitcnt vmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3])
+        : "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3])
+        : "memory");
+  } else if constexpr (K <= 8) {
+    asm volatile(
+        "global_load_dwordx4 %0, %8, off sc1\n\t"
+        "global_load_dwordx4 %1, %9, off sc1\n\t"
+        "global_load_dwordx4 %2, %10, off sc1\n\t"
+        "global_load_dwordx4 %3, %11, off sc1\n\t"
+        "global_load_dwordx4 %4, %12, off sc1\n\t"
+        "global_load_dwordx4 %5, %13, off sc1\n\t"
+        "global_load_dwordx4 %6, %14, off sc1\n\t"
+        "global_load_dwordx4 %7, %15, off sc1\n\t"
+        "s_waitcnt vmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]),
+          "=&v"(r[7])
+        : "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), "v"(p[6]), "v"(p[7])
+        : "memory");
+  } else {
+    asm volatile(
+        "global_load_dwordx4 %0, %12, off sc1\n\t"
+        "global_load_dwordx4 %1, %13, off sc1\n\t"
+        "global_load_dwordx4 %2, %14, off sc1\n\t"
+        "global_load_dwordx4 %3, %15, off sc1\n\t"
+        "global_load_dwordx4 %4, %16, off sc1\n\t"
+        "global_load_dwordx4 %5, %17, off sc1\n\t"
+        "global_load_dwordx4 %6, %18, off sc1\n\t"
+        "global_load_dwordx4 %7, %19, off sc1\n\t"
+        "global_load_dwordx4 %8, %20, off sc1\n\t"
+        "global_load_dwordx4 %9, %21, off sc1\n\t"
+        "global_load_dwordx4 %10, %22, off sc1\n\t"
+        "global_load_dwordx4 %11, %23, off sc1\n\t"
+        "s_waitcnt vmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]),
+          "=&v"(r[7]), "=&v"(r[8]), "=&v"(r[9]), "=&v"(r[10]), "=&v"(r[11])
+        : "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), "v"(p[6]), "v"(p[7]), "v"(p[8]),
+          "v"(p[9]), "v"(p[10]), "v"(p[11])
+        : "memory");
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) out[i] = r[i];
 }
+
 __device__ __forceinline__ double chunk_val(v4i x) { return __hiloint2double(x[1], x[0]); }
 
 constexpr unsigned off_hdr(int par, int w) {
@@ -179,13 +255,11 @@ struct PanelShared {
 // Bounded poll of n chunks (lane i of the calling wave reads offs[i]) until all
 // tags match; returns the chunks.  Lanes may repeat offsets.
 template <int K>
-__device__ __forceinline__ void poll_chunks(__amdgpu_buffer_rsrc_t rs, const unsigned (&offs)[K], v4i (&out)[K],
+__device__ __forceinline__ void poll_chunks(const char* base, const unsigned (&offs)[K], v4i (&out)[K],
                                             unsigned tag, int lane, int32_t* info) {
   long long spins = 0;
   while (true) {
-    __asm__ volatile("" ::: "memory");   // the polled chunks change under us: reload on every pass
-#pragma unroll
-    for (int i = 0; i < K; ++i) out[i] = get_chunk(rs, offs[i]);
+    get_chunks<K>(base, offs, out);
     unsigned bad = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) bad |= (unsigned)out[i][3] ^ tag;
@@ -208,12 +282,10 @@ struct Panel {
   int nwg, wg, tid, lane, wave;
   unsigned epoch;
   __amdgpu_buffer_rsrc_t rs;
+  const char* wbase;
   double (*s_cand)[NWAVE][BW];
   double (*s_drow)[BW];
   double (*s_prow)[BW];
-  double (*s_wrow)[BW];
-  double (*s_lrow)[BW];
-  double (*s_ldrow)[BW];
   PanelShared* sh;
   double v[2][BW];
   int rows[2];
@@ -281,7 +353,7 @@ struct Panel {
       sh->val[par][wave] = bv;
       sh->row[par][wave] = br;
     }
-    __syncthreads();
+    lds_sync();
     double wv[NWAVE];
     int wr[NWAVE];
 #pragma unroll
@@ -363,7 +435,7 @@ struct Panel {
                 const int f = min(lane + kWave * i, nwg * BW - 1);
                 offs[2 + i] = off_cand(par, f / BW, f % BW);
               }
-              poll_chunks<kPoll + 2>(rs, offs, got, tag, lane, info);
+              poll_chunks<kPoll + 2>(wbase, offs, got, tag, lane, info);
               double gv = lane < nwg ? chunk_val(got[0]) : -1.0;
               int gr = lane < nwg ? got[0][2] : kRowNone;
               wave_argmax(gv, gr);
@@ -376,7 +448,7 @@ struct Panel {
               }
               if (lane < BW) s_drow[par][lane] = chunk_val(got[1]);
             }
-            __syncthreads();
+            lds_sync();
             p = sh->p[par];
             prow = s_prow[par];
           }
@@ -394,83 +466,109 @@ struct Panel {
   // operations only and publishes the pivot row.  Every other wave follows on
   // its own, with no barrier: it fetches the pivot rows of a whole group of U
   // columns at once (one memory round trip when the leader is ahead), checks
-  // and updates its rows.
+  // and updates its rows.  The two roles run separate loops: the leader's loop
+  // issues stores only and never waits for them; the followers' loop loads only.
   __device__ __forceinline__ int spec_pass() {
+    __builtin_amdgcn_s_waitcnt(0);   // the block's loads, before loops that must not wait in them
+    if (wg == 0 && wave == 0) {
+      spec_lead();
+      return bw;   // the leader's rows never beat the maximum it chose
+    }
+    return spec_follow();
+  }
+
+  // The leader's column step uses cross-lane operations only (its rows are its
+  // lanes): the two rows are interchanged with a lane permutation, the pivot
+  // row is broadcast into scalar registers, published by lanes 0..BW-1, and
+  // the leader's rows below the pivot are updated.
+  __device__ __forceinline__ void spec_lead() {
+    for (int c0 = 0; c0 < bw; c0 += U) {
+      const int lim = bw - c0;
+      static_for<U>([&](auto uidx) {
+        constexpr int u = decltype(uidx)::value;
+        const int c = c0 + u;
+        if (c < bw) {
+          const unsigned tag = epoch * 64u + (unsigned)c;
+          const bool act = rows[0] < m && rows[0] >= c;
+          double bv = act ? fabs(v[0][u]) : -1.0;
+          int br = act ? rows[0] : kRowNone;
+          wave_argmax(bv, br);
+          const int p = br;   // leader rows are lanes: row p sits in lane p
+          if (p != c) {
+            const int src = lane == c ? p : (lane == p ? c : lane);
+#pragma unroll
+            for (int j = 0; j < BW; ++j) v[0][j] = bpermute_f64(src, v[0][j]);
+          }
+          double pr[BW];
+#pragma unroll
+          for (int j = 0; j < BW; ++j) pr[j] = (j < u) ? 0.0 : readlane_f64(v[0][j], c);
+          double out = 0.0;
+#pragma unroll
+          for (int j = 0; j < BW; ++j) out = lane == j ? pr[j] : out;
+          if (lane < BW) put_chunk(rs, off_spec(c, lane), out, 0u, tag);
+          const double piv = pr[u];
+          if (rows[0] > c && rows[0] < m) {
+            double l = v[0][u];
+            if (piv != 0.0) {
+              l = l / piv;
+              v[0][u] = l;
+            }
+#pragma unroll
+            for (int j = u + 1; j < BW; ++j) v[0][j] = v[0][j] - l * ((j < lim) ? pr[j] : 0.0);
+          }
+          if (lane == 0) {
+            sh->piv[c] = p;
+            if (piv == 0.0 && sh->zero_col < 0) sh->zero_col = c;
+          }
+        }
+      });
+      rotate();
+    }
+    unrotate();
+  }
+
+  __device__ __forceinline__ int spec_follow() {
     int fail = bw;
-    const bool leader = (wg == 0 && wave == 0);
     for (int c0 = 0; c0 < bw; c0 += U) {
       const int lim = bw - c0;
       v4i cache[U];
       static_for<U>([&](auto uidx) {
         constexpr int u = decltype(uidx)::value;
-        constexpr int par = u & 1;
         const int c = c0 + u;
         if (c < bw) {
           const unsigned tag = epoch * 64u + (unsigned)c;
-          if (leader) {
-            const bool act = rows[0] < m && rows[0] >= c;
-            double bv = act ? fabs(v[0][u]) : -1.0;
-            int br = act ? rows[0] : kRowNone;
-            wave_argmax(bv, br);
-            const int p = br;
-            double* lp = s_lrow[par];
-            double* ld = s_ldrow[par];
-            if (rows[0] == p) lds_put_row<BW>(lp, v[0]);
-            if (rows[0] == c) lds_put_row<BW>(ld, v[0]);
-            __builtin_amdgcn_wave_barrier();   // a wave's LDS accesses complete in order
-            if (lane < BW) put_chunk(rs, off_spec(c, lane), lp[lane], 0u, tag);
-            const double piv = lp[u];
-            if (rows[0] == c) lds_get_row<BW>(v[0], lp);
-            else if (rows[0] == p) lds_get_row<BW>(v[0], ld);
-            if (rows[0] > c && rows[0] < m) {
-              double l = v[0][u];
+          unsigned offs[U];
+#pragma unroll
+          for (int i = 0; i < U; ++i) offs[i] = off_spec(min(c0 + i, bw - 1), lane % BW);
+          if (u == 0) get_chunks<U>(wbase, offs, cache);   // the whole group's pivot rows in one go
+          long long spins = 0;
+          while (!__all((unsigned)cache[u][3] == tag)) {
+            __builtin_amdgcn_s_sleep(1);
+            get_chunks<U>(wbase, offs, cache);
+            if (++spins > kSpinLimit) {
+              if (lane == 0) atomicExch(info, -999);
+              break;
+            }
+          }
+          // lane j holds entry j of the pivot row: broadcast it
+          const double mine = chunk_val(cache[u]);
+          double pr[BW];
+#pragma unroll
+          for (int j = 0; j < BW; ++j) pr[j] = (j < u) ? 0.0 : readlane_f64(mine, j);
+          const double piv = pr[u];
+          const double apiv = fabs(piv);
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const int r = rows[k];
+            if (r < m) {
+              if (fabs(v[k][u]) > apiv && fail > c) fail = c;
+              double l = v[k][u];
               if (piv != 0.0) {
                 l = l / piv;
-                v[0][u] = l;
+                v[k][u] = l;
               }
 #pragma unroll
-              for (int j = u + 1; j < BW; ++j) v[0][j] = v[0][j] - l * ((j < lim) ? lp[j] : 0.0);
-            }
-            if (lane == 0) {
-              sh->piv[c] = p;
-              if (piv == 0.0 && sh->zero_col < 0) sh->zero_col = c;
-            }
-          } else {
-            if (u == 0) {   // fetch the whole group's pivot rows in one go
-#pragma unroll
-              for (int i = 0; i < U; ++i) cache[i] = get_chunk(rs, off_spec(min(c0 + i, bw - 1), lane % BW));
-            }
-            long long spins = 0;
-            while (!__all((unsigned)cache[u][3] == tag)) {
-              __builtin_amdgcn_s_sleep(1);
-              __asm__ volatile("" ::: "memory");   // re-read the chunks not yet published
-#pragma unroll
-              for (int i = u; i < U; ++i) cache[i] = get_chunk(rs, off_spec(min(c0 + i, bw - 1), lane % BW));
-              if (++spins > kSpinLimit) {
-                if (lane == 0) atomicExch(info, -999);
-                break;
-              }
-            }
-            // lane j holds entry j: stage the row in this wave's own LDS row
-            // (a wave's LDS accesses complete in order) and read it back
-            double* pr = s_wrow[wave];
-            if (lane < BW) pr[lane] = chunk_val(cache[u]);
-            __builtin_amdgcn_wave_barrier();
-            const double piv = pr[u];
-            const double apiv = fabs(piv);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-              const int r = rows[k];
-              if (r < m) {
-                if (fabs(v[k][u]) > apiv && fail > c) fail = c;
-                double l = v[k][u];
-                if (piv != 0.0) {
-                  l = l / piv;
-                  v[k][u] = l;
-                }
-#pragma unroll
-                for (int j = u + 1; j < BW; ++j) v[k][j] = v[k][j] - l * ((j < lim) ? pr[j] : 0.0);
-              }
+              for (int j = u + 1; j < BW; ++j) v[k][j] = v[k][j] - l * ((j < lim) ? pr[j] : 0.0);
             }
           }
         }
@@ -485,7 +583,7 @@ struct Panel {
   __device__ __forceinline__ int verify(int fail) {
     const int wf = wave_min_int(fail);
     if (lane == 0) sh->fail[wave] = wf;
-    __syncthreads();
+    lds_sync();
     if (wave == 0) {
       int f = sh->fail[0];
 #pragma unroll
@@ -495,11 +593,11 @@ struct Panel {
     } else if (wave == 1) {
       unsigned offs[1] = {off_verify(min(lane, nwg - 1))};
       v4i got[1];
-      poll_chunks<1>(rs, offs, got, epoch * 64u + kTagVerify, lane, info);
+      poll_chunks<1>(wbase, offs, got, epoch * 64u + kTagVerify, lane, info);
       const int g = wave_min_int((int)chunk_val(got[0]));
       if (lane == 0) sh->gfail = g;
     }
-    __syncthreads();
+    lds_sync();
     return sh->gfail;
   }
 };
@@ -512,9 +610,6 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   __shared__ __attribute__((aligned(16))) double s_cand[2][NWAVE][BW];
   __shared__ __attribute__((aligned(16))) double s_drow[2][BW];
   __shared__ __attribute__((aligned(16))) double s_prow[2][BW];
-  __shared__ __attribute__((aligned(16))) double s_wrow[NWAVE][BW];
-  __shared__ __attribute__((aligned(16))) double s_lrow[2][BW];
-  __shared__ __attribute__((aligned(16))) double s_ldrow[2][BW];
   __shared__ PanelShared sh;
 
   Panel<BW, MAXW> P;
@@ -530,12 +625,10 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   P.wave = threadIdx.x >> 6;
   P.epoch = epoch;
   P.rs = rsrc_of(work);
+  P.wbase = reinterpret_cast<const char*>(work);
   P.s_cand = s_cand;
   P.s_drow = s_drow;
   P.s_prow = s_prow;
-  P.s_wrow = s_wrow;
-  P.s_lrow = s_lrow;
-  P.s_ldrow = s_ldrow;
   P.sh = &sh;
   if (P.wg == 0) {
     P.rows[0] = P.tid;
@@ -556,14 +649,14 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
       if (P.wg == 0 && P.tid == 0) work->spec_off = 1u;
       if (P.tid == 0) sh.zero_col = -1;
       P.load();
-      __syncthreads();
+      lds_sync();
     }
   }
   if (!done) P.exact_pass();
 
   P.store();
   if (P.wg == 0) {
-    __syncthreads();
+    lds_sync();
     for (int c = P.tid; c < bw; c += NT) ipiv[c] = row0 + sh.piv[c] + 1;
     if (P.tid == 0 && sh.zero_col >= 0) atomicCAS(info, 0, row0 + sh.zero_col + 1);
   }

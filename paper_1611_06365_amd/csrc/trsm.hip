@@ -38,10 +38,28 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
   }
 
   const int nblk = (nr + kDiag - 1) / kDiag;
+  constexpr int kItems = 2 * (kRows / 16) / 4;   // update items per wave, at most
   for (int step = 0; step < nblk; ++step) {
     const int blk = LOWER ? step : nblk - 1 - step;
     const int ib = blk * kDiag;
     const int bs = min(kDiag, nr - ib);
+    // rows still to be solved: below the block (lower) or above it (upper);
+    // this wave's update items are (16-row block, 16-column half) pairs, and
+    // their -T entries are fetched now, so the loads overlap the block solve
+    const int rlo = LOWER ? ib + kDiag : 0;
+    const int rhi = LOWER ? nr : ib;
+    const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
+    double ta[kItems][4];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const int item = wave + 4 * i;
+      const int tr = rlo + (item >> 1) * 16 + li;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = 4 * lq + st;   // MFMA step st feeds lane group lq with k = 4 lq + st
+        ta[i][st] = (item < 2 * nrb && tr < nr && k < bs) ? -T[(size_t)tr * ldt + ib + k] : 0.0;
+      }
+    }
     // T's diagonal block -> LDS
     {
       const int r = tid / kDiag, c = tid % kDiag;
@@ -82,25 +100,22 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
         if (r < bs) X[(ib + r) * kPitch + tid] = x[r];
     }
     __syncthreads();
-    // rows still to be solved: below the block (lower) or above it (upper)
-    const int rlo = LOWER ? ib + kDiag : 0;
-    const int rhi = LOWER ? nr : ib;
-    const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
-    for (int item = wave; item < 2 * nrb; item += 4) {
-      const int R0 = rlo + (item >> 1) * 16, ch = (item & 1) * 16;
-      v4d acc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = X[(R0 + lq + 4 * r) * kPitch + ch + li];
-      const int tr = R0 + li;
+    for (int i = 0; i < kItems; ++i) {
+      const int item = wave + 4 * i;
+      if (item < 2 * nrb) {
+        const int R0 = rlo + (item >> 1) * 16, ch = (item & 1) * 16;
+        v4d acc;
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int k = 4 * lq + st;   // MFMA step st feeds lane group lq with k = 4 lq + st
-        const double a = (tr < nr && k < bs) ? -T[(size_t)tr * ldt + ib + k] : 0.0;
-        const double b = X[(ib + k) * kPitch + ch + li];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) acc[r] = X[(R0 + lq + 4 * r) * kPitch + ch + li];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const double b = X[(ib + 4 * lq + st) * kPitch + ch + li];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[i][st], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) X[(R0 + lq + 4 * r) * kPitch + ch + li] = acc[r];
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) X[(R0 + lq + 4 * r) * kPitch + ch + li] = acc[r];
     }
     __syncthreads();
   }
