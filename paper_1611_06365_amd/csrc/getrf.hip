@@ -43,7 +43,10 @@ struct AuxStreams {
 // shader engine (4 per XCD per unit, 32 per unit on the chip) to the panel
 // factorization, whose register-resident kernel needs whole CUs; once PF3 is
 // done, kLaHelpers workgroups on the panel's stream join RU2's tile queue.
-constexpr int kLaReserve = 1;
+#ifndef MLU_LA_RESERVE
+#define MLU_LA_RESERVE 1
+#endif
+constexpr int kLaReserve = MLU_LA_RESERVE;
 constexpr int kLaHelpers = 64 * kLaReserve;
 std::mutex g_aux_mu;
 AuxStreams g_aux[64];
@@ -90,14 +93,15 @@ struct Ctx {
 hipError_t factor_panel(hipStream_t s, const Ctx& c, int j, int b) {
   for (int jj = j; jj < j + b; jj += c.bi) {
     const int bw = (j + b - jj) < c.bi ? (j + b - jj) : c.bi;
-    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch));
-    MLU_TRY(laswp(s, c.A, c.lda, c.m, jj, jj + bw, c.ipiv, j, jj, jj + bw, j + b, c.info));
+    // the register-resident kernel also applies the block's interchanges to
+    // the panel's other columns and solves the block's rows of the columns to
+    // its right (the inner RL2); the inner RL3 follows
     const int rest = j + b - jj - bw;
-    if (rest > 0) {
-      MLU_TRY(trsm_left(s, true, true, bw, rest, c.at(jj, jj), c.lda, c.at(jj, jj + bw), c.lda));
+    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, jj - j,
+                         rest));
+    if (rest > 0 && jj + bw < c.m)
       MLU_TRY(gemm_update(s, c.m - jj - bw, rest, bw, c.at(jj + bw, jj), c.lda, c.at(jj, jj + bw), c.lda,
                           c.at(jj + bw, jj + bw), c.lda));
-    }
   }
   return hipSuccess;
 }

@@ -87,9 +87,13 @@ hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 // block only; ipiv[row0 + c] = row0 + p + 1 (1-based); a zero pivot sets
 // *info = row0 + c + 1 if *info was 0.
 // `epoch` must differ between the launches of one call (the exchange area is
-// cleared at the start of the call).
+// cleared at the start of the call).  When the block lies inside a wider panel
+// (cl columns of it to the block's left, cr to its right, same rows), the
+// block's interchanges are also applied to those columns and the block's top
+// bw rows of the right columns are solved with its unit lower triangle.
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0,
-                        int32_t* ipiv, int32_t* info, PanelWork* work, unsigned epoch);
+                        int32_t* ipiv, int32_t* info, PanelWork* work, unsigned epoch, int cl = 0,
+                        int cr = 0);
 
 // Apply interchanges ipiv[k1 .. k2) (1-based values, each >= its own index and
 // < m) to columns [ca0, ca1) and [cb0, cb1) of the m-row matrix A.

@@ -602,10 +602,109 @@ struct Panel {
   }
 };
 
+// Epilogue of worker 0 when the block is part of a wider panel: the block's
+// interchanges applied to the panel's other columns (cl columns to the left of
+// the block, cr to its right; LAPACK laswp semantics, the sequential swaps
+// composed into one permutation of the touched rows and every displaced row
+// segment moved once through LDS), then the block's top rows of the cr right
+// columns solved with the block's unit lower triangle (A12 := trilu(A11)^-1 A12,
+// the next step of the blocked RL algorithm inside the panel).  No other
+// worker touches these columns during the launch.
+constexpr int kMvCols = 64;
+
+struct EpilogueShared {
+  double mv[2 * kPanelRegCols][kMvCols];
+  double L[kPanelRegCols][kPanelRegCols + 1];
+  int slot[kPanelRegCols];
+  int row[2 * kPanelRegCols];
+  int label[2 * kPanelRegCols];
+  int any;
+};
+
+// Kept out of line so that its registers do not add to the factorization's;
+// es.L already holds the block's strictly lower rows 0..bw-1.
+template <int BW>
+__device__ __noinline__ void panel_epilogue(double* __restrict__ A, int lda, int bw, int cl, int cr,
+                                            const int* piv, int tid, EpilogueShared* esp) {
+  EpilogueShared& es = *esp;
+  const int ntouch = 2 * bw;
+  if (tid < ntouch) {
+    es.label[tid] = tid;
+    es.row[tid] = tid < bw ? tid : -1;
+  }
+  if (tid == 0) es.any = 0;
+  __syncthreads();
+  if (tid < bw) {   // slot of step tid's partner row
+    const int p = piv[tid];
+    int slot;
+    if (p < bw) {
+      slot = p;
+    } else {
+      int first = tid;
+      for (int q = 0; q < tid; ++q)
+        if (piv[q] == p) {
+          first = q;
+          break;
+        }
+      slot = bw + first;
+      if (first == tid) es.row[bw + tid] = p;
+    }
+    es.slot[tid] = slot;
+    if (p != tid) es.any = 1;
+  }
+  __syncthreads();
+  if (es.any) {
+    if (tid == 0) {
+      for (int c = 0; c < bw; ++c) {
+        const int t = es.label[c];
+        es.label[c] = es.label[es.slot[c]];
+        es.label[es.slot[c]] = t;
+      }
+    }
+    __syncthreads();
+    const int ncols = cl + cr;
+    for (int c0 = 0; c0 < ncols; c0 += kMvCols) {
+      const int cc = tid % kMvCols;
+      const int g = c0 + cc;
+      const int col = g < cl ? g - cl : bw + (g - cl);   // relative to the block's first column
+      for (int sl = tid / kMvCols; sl < ntouch; sl += NT / kMvCols) {
+        const int src = es.label[sl];
+        if (g < ncols && es.row[sl] >= 0 && src != sl) es.mv[sl][cc] = A[(size_t)es.row[src] * lda + col];
+      }
+      __syncthreads();
+      for (int sl = tid / kMvCols; sl < ntouch; sl += NT / kMvCols) {
+        const int src = es.label[sl];
+        if (g < ncols && es.row[sl] >= 0 && src != sl) A[(size_t)es.row[sl] * lda + col] = es.mv[sl][cc];
+      }
+      __syncthreads();
+    }
+  }
+  // A12 := trilu(A11)^-1 A12 on the right columns, one column per thread
+  for (int j = tid; j < cr; j += NT) {
+    double x[BW];
+    double* colp = A + bw + j;
+#pragma unroll
+    for (int r = 0; r < BW; ++r) x[r] = (r < bw) ? colp[(size_t)r * lda] : 0.0;
+#pragma unroll
+    for (int r = 1; r < BW; ++r) {
+      if (r < bw) {
+        double v = x[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) v = v - es.L[r][q] * x[q];
+        x[r] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 1; r < BW; ++r)
+      if (r < bw) colp[(size_t)r * lda] = x[r];
+  }
+}
+
 template <int BW, int MAXW>
 __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
                                               int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
-                                              PanelWork* __restrict__ work, int nwg, unsigned epoch) {
+                                              PanelWork* __restrict__ work, int nwg, unsigned epoch, int cl,
+                                              int cr) {
   static_assert(BW % U == 0, "BW must be a multiple of U");
   __shared__ __attribute__((aligned(16))) double s_cand[2][NWAVE][BW];
   __shared__ __attribute__((aligned(16))) double s_drow[2][BW];
@@ -659,32 +758,40 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
     lds_sync();
     for (int c = P.tid; c < bw; c += NT) ipiv[c] = row0 + sh.piv[c] + 1;
     if (P.tid == 0 && sh.zero_col >= 0) atomicCAS(info, 0, row0 + sh.zero_col + 1);
+    if (cl > 0 || cr > 0) {
+      __shared__ EpilogueShared es;
+      if (P.tid < bw) {
+#pragma unroll
+        for (int c = 0; c < BW; ++c) es.L[P.tid][c] = (c < P.tid) ? P.v[0][c] : 0.0;
+      }
+      panel_epilogue<BW>(A, lda, bw, cl, cr, sh.piv, P.tid, &es);
+    }
   }
 }
 
 template <int BW>
 hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr) {
   const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
   if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
   if (nwg <= 16)
     hipLaunchKernelGGL((k_panel<BW, 16>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, nwg,
-                       epoch);
+                       epoch, cl, cr);
   else
     hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
-                       work, nwg, epoch);
+                       work, nwg, epoch, cl, cr);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr) {
   if (m <= 0 || bw <= 0) return hipSuccess;
-  if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows) return hipErrorInvalidValue;
+  if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows || cl < 0 || cr < 0) return hipErrorInvalidValue;
   ipiv += row0;
-  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch);
-  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch);
+  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr);
+  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr);
 }
 
 size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }
