@@ -99,6 +99,78 @@ def cpu_baseline(n: int):
     }
 
 
+def mixed_section(args, dev):
+    """FP32-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
+    solve (the same entry point with FP64 products and no correction: getrf,
+    getrs, one residual) on A = Q diag(sv) Q^T, Q Haar, for several condition
+    numbers; one right-hand side b ~ N(0, 1).  Both timed with HIP events on
+    the current stream, inputs resident, the best of a few runs."""
+    import torch
+
+    import inputs.device as D
+    from paper_1611_06365_amd import mlu
+
+    n = args.n
+    log(f"mixed: Haar Q of order {n}")
+    q = D.haar_orthogonal(n, seed=0, device=dev)
+    b = D.gaussian_rhs(n, 1, seed=1, device=dev)
+    rc, nbytes = mlu.mlu_dsgesv_ir_workspace(n, 1)
+    mlu.check(rc, "mlu_dsgesv_ir_workspace")
+    work_ir = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    x64 = torch.empty((n, 1), dtype=torch.float64, device=dev)
+    xmp = torch.empty((n, 1), dtype=torch.float64, device=dev)
+
+    def timed(fn, reps=2):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    def berr_of(A, x):
+        r = b - A @ x
+        an = A.abs().sum(dim=1).max()
+        return float(r.abs().max() / (an * x.abs().max() + b.abs().max()))
+
+    cases = []
+    for cond in [float(c) for c in args.mixed_conds.split(",")]:
+        A = D.spectrum_matrix(q, cond)
+        torch.cuda.synchronize()
+        out = {}
+
+        def fp64():   # the same solver with FP64 products and no correction: getrf + getrs + one residual
+            out["r64"] = mlu.gesv_ir(A, b, precision="fp64", tol=1e-13, max_iter=0, variant=args.variant,
+                                     nb=args.nb, nb_inner=args.nb_inner, X=x64, work=work_ir)
+
+        def mixedrun():
+            out["r"] = mlu.gesv_ir(A, b, precision="fp32", tol=1e-13, max_iter=10, variant=args.variant, nb=args.nb,
+                                   nb_inner=args.nb_inner, X=xmp, work=work_ir)
+
+        fp64()   # warm-up
+        mixedrun()
+        t64 = timed(fp64)
+        tmp = timed(mixedrun)
+        _, _, minfo, iters, berr = out["r"]
+        case = {"cond": cond, "ms_fp64_solve": round(t64, 3), "ms_mixed_ir": round(tmp, 3),
+                "speedup": round(t64 / tmp, 3), "iters": int(iters.item()), "berr": float(berr.item()),
+                "berr_fp64_solve": float(out["r64"][4].item()), "berr_fp64_recomputed": berr_of(A, x64),
+                "berr_recomputed": berr_of(A, xmp), "info": int(minfo.item()),
+                "rel_diff_vs_fp64_solve": float((xmp - x64).abs().max() / x64.abs().max())}
+        log(f"mixed cond={cond:g}: {case}")
+        cases.append(case)
+        del A
+    return {"what": "FP32-product trailing updates (FP64 panel, solves, residual, correction) + FP64 "
+                    "iterative refinement to backward error <= 1e-13, vs the FP64 solve (getrf + getrs + residual)",
+            "n": n, "nrhs": 1, "matrix": "Q diag(logspace(0,-log10 cond,n)) Q^T, Q Haar (seed 0), b ~ N(0,1)",
+            "cases": cases}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +183,9 @@ def main() -> int:
     ap.add_argument("--matrix", default="spd", choices=["spd", "uniform"])
     ap.add_argument("--cpu-n", type=int, default=8192, help="size of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision + refinement measurement")
+    ap.add_argument("--mixed-conds", default="1e2,1e5,1e8")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -206,6 +281,12 @@ def main() -> int:
             "share_of_step_time": round(gemm_ms / ms, 4),
         }
 
+    mixed = None
+    if not args.no_mixed:
+        del copies
+        torch.cuda.empty_cache()
+        mixed = mixed_section(args, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: C oracle on n={args.cpu_n}")
@@ -237,6 +318,7 @@ def main() -> int:
         },
         "frac_fp64_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
         "roofline": roof,
+        "mixed": mixed,
         "cpu_baseline": cpu,
         "check": check,
     }

@@ -49,6 +49,19 @@ enum mlu_variant {
   MLU_LA = 2  /* right-looking with look-ahead: T_PF (PF1-PF3) || T_RU (RU1-RU2)      */
 };
 
+/*
+ * Precision of the products in the outer trailing updates (RL3, PF2, RU2, LL2)
+ * of the mixed-precision factorization.  The matrix stays FP64 in memory: the
+ * operands of each update are rounded to the lower precision, the product is
+ * accumulated in it (FP32 matrix cores), and it is subtracted from the FP64
+ * trailing matrix.  The panel factorization and its inner updates, the
+ * triangular solves and the interchanges stay FP64.
+ */
+enum mlu_precision {
+  MLU_PREC_FP64 = 0,
+  MLU_PREC_FP32 = 1
+};
+
 /* Largest panel block held in registers by the diagonal-block kernel. */
 #define MLU_MAX_NB_INNER 16
 
@@ -103,6 +116,46 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
 int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
                int variant, int nb, int nb_inner, const int32_t *h_schedule, int n_schedule,
                int iters_limit, void *d_work, size_t work_bytes);
+
+/*
+ * Mixed-precision LU with partial pivoting: mlu_dgetrf with the outer trailing
+ * updates' products in `precision` (MLU_PREC_FP32, or MLU_PREC_FP64 for
+ * exactly mlu_dgetrf).  The factors are those of a matrix within about
+ * u_low * ||A|| of A (u_low = 2^-24 for FP32) rather than u_64 * ||A||: meant
+ * as the factorization inside iterative refinement (mlu_dsgesv_ir), the
+ * precision ladder the paper's loop-based variants admit unchanged (Fig.
+ * "LU", Fig. "LU_la_blk": only the update kernel differs).  Arguments as
+ * mlu_dgetrf, with `precision` inserted as argument 11 (later arguments are
+ * numbered one higher in the -i return codes).
+ */
+int mlu_dsgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info, int variant,
+                int nb, int nb_inner, int precision, const int32_t *h_schedule, int n_schedule, int iters_limit,
+                void *d_work, size_t work_bytes);
+
+/*
+ * Solve A X = B by mixed-precision LU and FP64 iterative refinement (the
+ * precision ladder over the paper's variants; Section 3 for the
+ * factorization):
+ *   LU := A factored by mlu_dsgetrf(precision, variant, nb, nb_inner);
+ *   X  := U^-1 L^-1 P B;
+ *   repeat: R := B - A X in FP64;
+ *           berr := max_j ||R_j||_inf / (||A||_inf ||X_j||_inf + ||B_j||_inf);
+ *           stop if berr <= tol (or after max_iter corrections);
+ *           X := X + U^-1 L^-1 P R.
+ *  dA (n x n, lda), dB (n x nrhs, ldb): read only.  dX (n x nrhs, ldx): the
+ *  solution.  d_ipiv (int32[n]) and d_info as mlu_dgetrf, for the factors.
+ *  *d_iters = number of corrections applied when berr <= tol was reached (0 if
+ *  the first solve met it), or -1 if it was not reached after max_iter
+ *  corrections; *d_berr = berr of the X returned.  Everything is enqueued;
+ *  the stop test is a device flag that the rest of the enqueued loop reads.
+ *  d_work: mlu_dsgesv_ir_workspace(n, nrhs) bytes (it holds the n x n factors).
+ *  Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
+ */
+int mlu_dsgesv_ir_workspace(int n, int nrhs, size_t *bytes);
+int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, const double *dB, int ldb, double *dX,
+                  int ldx, int precision, double tol, int max_iter, int variant, int nb, int nb_inner,
+                  int32_t *d_ipiv, int32_t *d_info, int32_t *d_iters, double *d_berr, void *d_work,
+                  size_t work_bytes);
 
 /*
  * Triangular solve with several right-hand sides, left side, no transpose:

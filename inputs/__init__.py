@@ -13,4 +13,6 @@ from .matrices import (  # noqa: F401
     leader_perm,
     random_schedule,
     small_int_matrix,
+    haar_spectrum,
+    gaussian_rhs,
 )

@@ -33,3 +33,37 @@ def uniform01(n: int, seed: int = 0, device="cuda"):
     a = torch.rand(n, n, generator=_gen(seed + 7, device), dtype=torch.float64, device=device)
     a.clamp_(min=torch.finfo(torch.float64).tiny)
     return a
+
+
+def haar_orthogonal(n: int, seed: int = 0, device="cuda"):
+    """Q Haar-distributed orthogonal: QR of a Gaussian matrix with the column
+    signs fixed by diag(R) (float64 on `device`)."""
+    import torch
+
+    g = torch.randn(n, n, generator=_gen(seed + 11, device), dtype=torch.float64, device=device)
+    q, r = torch.linalg.qr(g)
+    del g
+    q.mul_(torch.sign(torch.diagonal(r))[None, :])
+    return q
+
+
+def spectrum_matrix(q, cond: float):
+    """A = Q diag(sv) Q^T with sv log-spaced from 1 to 1/cond."""
+    import math
+
+    import torch
+
+    n = q.shape[0]
+    sv = torch.logspace(0.0, -math.log10(float(cond)), n, dtype=torch.float64, device=q.device)
+    return (q * sv[None, :]) @ q.T.contiguous()
+
+
+def haar_spectrum(n: int, cond: float, seed: int = 0, device="cuda"):
+    """A = Q diag(sv) Q^T, Q Haar orthogonal, sv log-spaced from 1 to 1/cond."""
+    return spectrum_matrix(haar_orthogonal(n, seed, device), cond)
+
+
+def gaussian_rhs(n: int, nrhs: int = 1, seed: int = 1, device="cuda"):
+    import torch
+
+    return torch.randn(n, nrhs, generator=_gen(seed + 13, device), dtype=torch.float64, device=device)

@@ -23,6 +23,11 @@ known_answer(m, n, s)   A = Pi^T L U with dyadic L (|l| <= 7/8, entries k/8) and
 zero_column(n, s, c)    known_answer with row c of U set to zero: the pivot
                         candidates of column c are all exactly zero (info = c+1)
                         and elimination stays exact.
+haar_spectrum(n, k, s)  A = Q diag(sv) Q^T with Q Haar-distributed orthogonal (QR
+                        of a Gaussian matrix, column signs fixed by diag(R)) and
+                        sv log-spaced from 1 down to 1/k: 2-norm condition
+                        number k (the mixed-precision workload).
+gaussian_rhs(n, r, s)   right-hand sides ~ N(0, 1), n x r.
 """
 from __future__ import annotations
 
@@ -146,3 +151,16 @@ def random_schedule(total: int, seed: int = 0, max_b: int = 8) -> list[int]:
         out.append(b)
         left -= b
     return out
+
+
+def haar_spectrum(n: int, cond: float, seed: int = 0) -> np.ndarray:
+    rng = _rng(seed, 11)
+    g = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))[None, :]
+    sv = np.logspace(0.0, -np.log10(float(cond)), n)
+    return np.ascontiguousarray((q * sv[None, :]) @ q.T)
+
+
+def gaussian_rhs(n: int, nrhs: int = 1, seed: int = 1) -> np.ndarray:
+    return np.ascontiguousarray(_rng(seed, 13).standard_normal((n, nrhs)))

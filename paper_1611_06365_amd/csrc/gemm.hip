@@ -198,6 +198,135 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
   }
 }
 
+// The same 128 x 128 tile with the product in FP32: A and B are rounded to
+// FP32 as they are staged into LDS, v_mfma_f32_16x16x4f32 accumulates in FP32
+// over the whole inner dimension, and the epilogue subtracts the product from
+// the FP64 C.  Used for the outer trailing updates of the mixed-precision
+// factorization (the panel and its inner updates stay FP64).  Accumulator
+// layout of the 16 x 16 f32 block (measured on gfx950): lane (li, lq) holds
+// rows 4 lq + r (r = 0..3) of column li.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int LDSF_A = BK + 4;   // floats per A row in LDS
+constexpr int LDSF_B = BN + 4;
+
+template <bool VEC>
+__device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                              int lda, const double* __restrict__ B, int ldb,
+                                              double* __restrict__ C, int ldc) {
+  __shared__ __attribute__((aligned(16))) float Asf[2][BM * LDSF_A];
+  __shared__ __attribute__((aligned(16))) float Bsf[2][BK * LDSF_B];
+
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ar = tid >> 1, ac = (tid & 1) * 8;
+  const int br = tid >> 4, bc = (tid & 15) * 8;
+  const bool interior_mn = (row0 + BM <= m) && (col0 + BN <= n);
+
+  double ra[8], rb[8];
+  auto gload = [&](int k0) {
+    const bool full = VEC && interior_mn && (k0 + BK <= k);
+    if (full) {
+      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double2 x = pa[e];
+        ra[2 * e] = x.x;
+        ra[2 * e + 1] = x.y;
+        double2 y = pb[e];
+        rb[2 * e] = y.x;
+        rb[2 * e + 1] = y.y;
+      }
+    } else {
+      const int gr = row0 + ar;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + ac + e;
+        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
+      const int gk = k0 + br;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gc = col0 + bc + e;
+        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    float* pa = &Asf[buf][ar * LDSF_A + ac];
+    float* pb = &Bsf[buf][br * LDSF_B + bc];
+#pragma unroll
+    for (int e = 0; e < 8; e += 4) {
+      *reinterpret_cast<float4*>(pa + e) =
+          make_float4((float)ra[e], (float)ra[e + 1], (float)ra[e + 2], (float)ra[e + 3]);
+      *reinterpret_cast<float4*>(pb + e) =
+          make_float4((float)rb[e], (float)rb[e + 1], (float)rb[e + 2], (float)rb[e + 3]);
+    }
+  };
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (k + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    float a[4][4], b[4][4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      const float4 a4 = *reinterpret_cast<const float4*>(&Asf[buf][(wm * 64 + blk * 16 + li) * LDSF_A + 4 * lq]);
+      a[blk][0] = a4.x;
+      a[blk][1] = a4.y;
+      a[blk][2] = a4.z;
+      a[blk][3] = a4.w;
+      const float* pb = &Bsf[buf][(4 * lq) * LDSF_B + wn * 64 + blk * 16 + li];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) b[blk][st] = pb[st * LDSF_B];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][st], b[j][st], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  double* const cbase = C + (size_t)(row0 + wm * 64 + 4 * lq) * ldc + col0 + wn * 64 + li;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 64 + i * 16 + 4 * lq + r;
+        const int col = col0 + wn * 64 + j * 16 + li;
+        if (interior_mn || (row < m && col < n)) {
+          double* pc = cbase + (size_t)(i * 16 + r) * ldc + j * 16;
+          *pc = *pc - (double)acc[i][j][r];
+        }
+      }
+}
+
+// one tile in the requested product precision
+template <bool VEC, int PREC>
+__device__ __forceinline__ void tile_any(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                         int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                         int ldc) {
+  if constexpr (PREC == kPrecF32) gemm_tile_f32<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  else gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
 // Generic launches (inner panel updates, blocked triangular solves) and the
 // outer trailing updates (RL3, PF2, RU2) run the same body under two kernel
 // names, so that a kernel trace separates the dominant launches.
@@ -205,19 +334,20 @@ template <bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_update(int m, int n, int k, const double* __restrict__ A,
                                                         int lda, const double* __restrict__ B, int ldb,
                                                         double* __restrict__ C, int ldc, int tiles_m,
-                                                        int tiles_n) {
+                                                        int tiles_n, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;   // a flag the caller raised on the device
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
   gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
-template <bool VEC>
+template <bool VEC, int PREC>
 __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, const double* __restrict__ A,
                                                           int lda, const double* __restrict__ B, int ldb,
                                                           double* __restrict__ C, int ldc, int tiles_m,
                                                           int tiles_n) {
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  tile_any<VEC, PREC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
 // Persistent form for the look-ahead variant's RU2: queue x holds the logical
@@ -226,7 +356,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, c
 // are exhausted.  Tickets past a queue's end are harmless (the counters are
 // cleared before the slot is used again).  No workgroup waits for another, so
 // the launch drains whatever runs beside it.
-template <bool VEC>
+template <bool VEC, int PREC>
 __global__ __launch_bounds__(256, 2) void k_gemm_queue(int m, int n, int k, const double* __restrict__ A,
                                                        int lda, const double* __restrict__ B, int ldb,
                                                        double* __restrict__ C, int ldc, int tiles_m,
@@ -256,7 +386,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_queue(int m, int n, int k, cons
     empty = 0;
     int tm, tn;
     group_coords(t, tiles_m, tiles_n, tm, tn);
-    gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+    tile_any<VEC, PREC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
   }
 }
 
@@ -286,7 +416,10 @@ void trace_slot(int m, int n, int k, hipEvent_t* e0, hipEvent_t* e1) {
 }  // namespace
 
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
-                       double* C, int ldc, bool trailing) {
+                       double* C, int ldc, bool trailing, int prec, bool traced, const int32_t* skip) {
+  if (skip != nullptr && trailing) return hipErrorInvalidValue;
+  if (prec != kPrecF64 && prec != kPrecF32) return hipErrorInvalidValue;
+  if (prec != kPrecF64 && !trailing) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
   const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
   const long long tiles = (long long)tiles_m * tiles_n;
@@ -294,18 +427,23 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
   const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
                    (lda % 2 == 0) && (ldb % 2 == 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (trailing) trace_slot(m, n, k, &e0, &e1);
+  if (trailing && traced) trace_slot(m, n, k, &e0, &e1);
   if (e0) {
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
   }
   const dim3 grid((unsigned)tiles), block(256);
   if (trailing) {
-    if (vec) hipLaunchKernelGGL(k_gemm_trailing<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
-    else hipLaunchKernelGGL(k_gemm_trailing<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    if (prec == kPrecF32) {
+      if (vec) hipLaunchKernelGGL((k_gemm_trailing<true, kPrecF32>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+      else hipLaunchKernelGGL((k_gemm_trailing<false, kPrecF32>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    } else {
+      if (vec) hipLaunchKernelGGL((k_gemm_trailing<true, kPrecF64>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+      else hipLaunchKernelGGL((k_gemm_trailing<false, kPrecF64>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    }
   } else {
-    if (vec) hipLaunchKernelGGL(k_gemm_update<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
-    else hipLaunchKernelGGL(k_gemm_update<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    if (vec) hipLaunchKernelGGL(k_gemm_update<true>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, skip);
+    else hipLaunchKernelGGL(k_gemm_update<false>, grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, skip);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
@@ -313,7 +451,9 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 }
 
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
-                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced) {
+                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
+                      int prec) {
+  if (prec != kPrecF64 && prec != kPrecF32) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) {
     if (clear == nullptr) return hipSuccess;
     m = n = k = 0;   // still clear the next slot
@@ -341,12 +481,21 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
   }
-  if (vec)
-    hipLaunchKernelGGL(k_gemm_queue<true>, dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m,
-                       tiles_n, q, clear, reserve);
-  else
-    hipLaunchKernelGGL(k_gemm_queue<false>, dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc,
-                       tiles_m, tiles_n, q, clear, reserve);
+  if (prec == kPrecF32) {
+    if (vec)
+      hipLaunchKernelGGL((k_gemm_queue<true, kPrecF32>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+    else
+      hipLaunchKernelGGL((k_gemm_queue<false, kPrecF32>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+  } else {
+    if (vec)
+      hipLaunchKernelGGL((k_gemm_queue<true, kPrecF64>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+    else
+      hipLaunchKernelGGL((k_gemm_queue<false, kPrecF64>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
   return e;

@@ -83,6 +83,7 @@ struct Ctx {
   int bi;
   PanelWork* work;
   QueueWork* queue;
+  int prec;          // product precision of the outer trailing updates
   unsigned* epoch;   // panel launch counter of this call (panels run one at a time)
   double* at(int i, int j) const { return A + (size_t)i * lda + j; }
 };
@@ -112,7 +113,7 @@ hipError_t update_cols(hipStream_t s, const Ctx& c, int j, int b, int c0, int c1
   MLU_TRY(trsm_left(s, true, true, b, c1 - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
   if (j + b < c.m)
     MLU_TRY(gemm_update(s, c.m - j - b, c1 - c0, b, c.at(j + b, j), c.lda, c.at(j, c0), c.lda, c.at(j + b, c0),
-                        c.lda, traced));
+                        c.lda, /*trailing=*/true, c.prec, traced));
   return hipSuccess;
 }
 
@@ -156,14 +157,14 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       MLU_TRY(hipEventRecord(aux->ru1, s0));
       const int mr = c.m - jn, nr = c.n - c0;
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
-                         kLaReserve, 0, true));
+                         kLaReserve, 0, true, c.prec));
       // T_PF: PF1, PF2, PF3, then it joins RU2's queue (after RU1 is done)
       MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
       MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));         // PF1, PF2
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false));
+                         0, kLaHelpers, false, c.prec));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
     } else {
@@ -193,7 +194,7 @@ hipError_t run_ll(hipStream_t s, const Ctx& c, const std::vector<int>& sched, in
       const int bl = sched[l];
       MLU_TRY(trsm_left(s, true, true, bl, b, c.at(jl, jl), c.lda, c.at(jl, j), c.lda));
       MLU_TRY(gemm_update(s, c.m - jl - bl, b, bl, c.at(jl + bl, jl), c.lda, c.at(jl, j), c.lda,
-                          c.at(jl + bl, j), c.lda, /*trailing=*/true));
+                          c.at(jl + bl, j), c.lda, /*trailing=*/true, c.prec));
       jl += bl;
     }
     MLU_TRY(factor_panel(s, c, j, b));                                           // LL3
@@ -236,9 +237,15 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
   return 0;
 }
 
-int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
-               int nb, int nb_inner, const int32_t* h_schedule, int n_schedule, int iters_limit, void* d_work,
-               size_t work_bytes) {
+}  // extern "C"
+
+namespace mlu {
+
+// mlu_dgetrf and mlu_dsgetrf; `sh` = 1 when called through mlu_dsgetrf, whose
+// arguments after `precision` (argument 11) are numbered one higher.
+int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
+                void* d_work, size_t work_bytes, int sh) {
   const int mn = m < n ? m : n;
   if (m < 0) return -2;
   if (n < 0) return -3;
@@ -249,14 +256,15 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   if (variant < MLU_RL || variant > MLU_LA) return -8;
   if (nb < 1) return -9;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32) return -11;
   if (h_schedule) {
-    if (n_schedule < 1) return -12;
+    if (n_schedule < 1) return -12 - sh;
     for (int i = 0; i < n_schedule; ++i)
-      if (h_schedule[i] < 1) return -11;
+      if (h_schedule[i] < 1) return -11 - sh;
   }
-  if (iters_limit < -1) return -13;
-  if (!d_work) return -14;
-  if (work_bytes < workspace_bytes()) return -15;
+  if (iters_limit < -1) return -13 - sh;
+  if (!d_work) return -14 - sh;
+  if (work_bytes < workspace_bytes()) return -15 - sh;
   if (m > kPanelMaxRows) return -2;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -278,7 +286,8 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   }
   unsigned epoch = 0;
   Workspace* ws = reinterpret_cast<Workspace*>(d_work);
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, &epoch};
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, precision == MLU_PREC_FP32 ? kPrecF32 : kPrecF64,
+        &epoch};
   c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
 
   hipError_t e;
@@ -286,6 +295,24 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   else if (variant == MLU_LA) e = run_la(s, c, sched, iters_limit);
   else e = run_ll(s, c, sched, iters_limit);
   return e == hipSuccess ? 0 : MLU_ERR_HIP;
+}
+
+}  // namespace mlu
+
+extern "C" {
+
+int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+               int nb, int nb_inner, const int32_t* h_schedule, int n_schedule, int iters_limit, void* d_work,
+               size_t work_bytes) {
+  return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, MLU_PREC_FP64, h_schedule,
+                     n_schedule, iters_limit, d_work, work_bytes, 0);
+}
+
+int mlu_dsgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
+                void* d_work, size_t work_bytes) {
+  return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision, h_schedule,
+                     n_schedule, iters_limit, d_work, work_bytes, 1);
 }
 
 int mlu_dtrsm(void* stream, char uplo, char diag, int m, int nrhs, const double* dT, int ldt, double* dB,

@@ -1,0 +1,308 @@
+// Mixed-precision LU with FP64 iterative refinement (the precision ladder over
+// the paper's LU variants): factor with FP32 products in the outer trailing
+// updates (mlu_dsgetrf), solve, then refine with FP64 residuals on the GPU:
+//   r = b - A x (FP64),  berr = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf),
+//   stop when berr <= tol, else solve (LU) d = P r and x := x + d.
+// Everything is enqueued on the caller's stream; convergence is a device flag
+// that the remaining launches of the refinement loop read, so that they do
+// nothing once it is raised (no host synchronization).
+#include "mlu_internal.h"
+#include "../../include/mlu.h"
+
+namespace mlu {
+namespace {
+
+// refinement state in the workspace (non-negative doubles as their bit
+// patterns, so that the maxima can be taken with integer atomics)
+struct IrState {
+  int32_t done;
+  int32_t pad;
+  unsigned long long anorm;
+};
+
+__device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
+__device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+#define MLU_IR_TRY(x)                   \
+  do {                                  \
+    hipError_t e__ = (x);               \
+    if (e__ != hipSuccess) return e__;  \
+  } while (0)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ void k_ir_copy(int rows, int cols, const double* __restrict__ src, int lds, double* __restrict__ dst,
+                          int ldd, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const size_t total = (size_t)rows * cols;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / cols, c = e % cols;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
+// ||A||_inf = max_i sum_j |a_ij|: one wave per row
+__global__ __launch_bounds__(256) void k_ir_anorm(int n, const double* __restrict__ A, int lda,
+                                                  unsigned long long* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const double* a = A + (size_t)row * lda;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += fabs(a[j]);
+  s = wave_sum(s);
+  if (lane == 0) atomicMax(out, dbits(s));
+}
+
+// out[c] = max_i |M[i][c]| for the nrhs columns
+__global__ __launch_bounds__(256) void k_ir_colmax(int n, int nrhs, const double* __restrict__ M, int ldm,
+                                                   unsigned long long* __restrict__ out,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / nrhs, c = e % nrhs;
+    atomicMax(&out[c], dbits(fabs(M[r * ldm + c])));
+  }
+}
+
+// Out = Y - A X, or Out = A X when Y is null (FP64; A rows x cols, X cols x
+// nrhs): one wave per row of A, right-hand sides in groups of 4.  Out may be Y
+// (each element is read and written by the same lane).  Serves as the
+// residual (A n x n) and as the block steps of the triangular solves.
+__global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, const double* __restrict__ A, int lda,
+                                              const double* __restrict__ X, int ldx, const double* Y, int ldy,
+                                              double* Out, int ldo, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const double* a = A + (size_t)row * lda;
+  for (int c0 = 0; c0 < nrhs; c0 += 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = lane; j < cols; j += 64) {
+      const double aj = a[j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (c0 + q < nrhs) s[q] += aj * X[(size_t)j * ldx + c0 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double t = wave_sum(s[q]);
+      if (lane == 0 && c0 + q < nrhs) {
+        const double y = Y != nullptr ? Y[(size_t)row * ldy + c0 + q] : 0.0;
+        Out[(size_t)row * ldo + c0 + q] = Y != nullptr ? y - t : t;
+      }
+    }
+  }
+}
+
+hipError_t gemv(hipStream_t s, int rows, int cols, int nrhs, const double* A, int lda, const double* X, int ldx,
+                const double* Y, int ldy, double* Out, int ldo, const int32_t* skip) {
+  if (rows <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemv, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, cols, nrhs, A, lda, X, ldx, Y,
+                     ldy, Out, ldo, skip);
+  return hipGetLastError();
+}
+
+// leading nr x nr of every 256 x 256 block := identity, the rest zero
+__global__ void k_identity_blocks(int n, double* __restrict__ Inv) {
+  const int nblk = (n + kInvBlock - 1) / kInvBlock;
+  const size_t total = (size_t)nblk * kInvBlock * kInvBlock;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = (e / kInvBlock) % kInvBlock, c = e % kInvBlock;
+    Inv[e] = r == c ? 1.0 : 0.0;
+  }
+}
+
+// B := U^-1 L^-1 P B with the inverted diagonal blocks (Linv, Uinv): per
+// 256-row block a GEMV with the block's inverse, then a GEMV update of the
+// rows still to be solved.  tmp: n x nrhs (leading dimension nrhs).
+hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int ld, const int32_t* ipiv,
+                         const double* Linv, const double* Uinv, double* Bx, int ldb, double* tmp,
+                         const int32_t* skip) {
+  if (laswp(s, Bx, ldb, n, 0, n, ipiv, 0, nrhs, 0, 0, nullptr, skip) != hipSuccess) return hipErrorUnknown;
+  const int nblk = (n + kInvBlock - 1) / kInvBlock;
+  const size_t bsz = (size_t)kInvBlock * kInvBlock;
+  for (int k = 0; k < nblk; ++k) {   // L: y := B (in place), x_k = Linv_k y_k -> tmp
+    const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
+    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Linv + k * bsz, kInvBlock, Bx + (size_t)r0 * ldb, ldb, nullptr, 0,
+                    tmp + (size_t)r0 * nrhs, nrhs, skip));
+    if (r0 + nbk < n)
+      MLU_IR_TRY(gemv(s, n - r0 - nbk, nbk, nrhs, LU + (size_t)(r0 + nbk) * ld + r0, ld, tmp + (size_t)r0 * nrhs,
+                      nrhs, Bx + (size_t)(r0 + nbk) * ldb, ldb, Bx + (size_t)(r0 + nbk) * ldb, ldb, skip));
+  }
+  for (int k = nblk - 1; k >= 0; --k) {   // U: z := tmp (in place), x_k = Uinv_k z_k -> B
+    const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
+    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Uinv + k * bsz, kInvBlock, tmp + (size_t)r0 * nrhs, nrhs, nullptr, 0,
+                    Bx + (size_t)r0 * ldb, ldb, skip));
+    if (r0 > 0)
+      MLU_IR_TRY(gemv(s, r0, nbk, nrhs, LU + r0, ld, Bx + (size_t)r0 * ldb, ldb, tmp, nrhs, tmp, nrhs, skip));
+  }
+  return hipSuccess;
+}
+
+// one thread: backward error of this round, stop test, and reset of the
+// per-round maxima
+__global__ void k_ir_check(int nrhs, IrState* st, unsigned long long* bnorm, unsigned long long* xnorm,
+                           unsigned long long* rnorm, double tol, int it, int max_iter, int32_t* d_iters,
+                           double* d_berr) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (st->done) return;
+  const double an = bitsd(st->anorm);
+  double berr = 0.0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double den = an * bitsd(xnorm[c]) + bitsd(bnorm[c]);
+    const double rn = bitsd(rnorm[c]);
+    const double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+    berr = (e > berr || e != e) ? e : berr;   // NaN propagates
+    xnorm[c] = 0ull;
+    rnorm[c] = 0ull;
+  }
+  *d_berr = berr;
+  if (berr <= tol) {
+    st->done = 1;
+    *d_iters = it;
+  } else if (it >= max_iter) {
+    st->done = 1;
+    *d_iters = -1;
+  }
+}
+
+__global__ void k_ir_axpy(int n, int nrhs, const double* __restrict__ D, int ldd, double* __restrict__ X, int ldx,
+                          const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const size_t total = (size_t)n * nrhs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = e / nrhs, c = e % nrhs;
+    X[r * ldx + c] += D[r * ldd + c];
+  }
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct IrLayout {
+  size_t lu, linv, uinv, r, t, state, norms, total;
+};
+IrLayout ir_layout(int n, int nrhs) {
+  IrLayout L;
+  const size_t inv = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(double);
+  L.lu = align_up(workspace_bytes());
+  L.linv = align_up(L.lu + (size_t)n * n * sizeof(double));
+  L.uinv = align_up(L.linv + inv);
+  L.r = align_up(L.uinv + inv);
+  L.t = align_up(L.r + (size_t)n * nrhs * sizeof(double));
+  L.state = align_up(L.t + (size_t)n * nrhs * sizeof(double));
+  L.norms = align_up(L.state + sizeof(IrState));
+  L.total = align_up(L.norms + 3 * (size_t)nrhs * sizeof(unsigned long long));
+  return L;
+}
+
+unsigned grid_for(size_t work) {
+  size_t g = (work + 255) / 256;
+  if (g > 65536) g = 65536;
+  return (unsigned)(g > 0 ? g : 1);
+}
+
+}  // namespace
+}  // namespace mlu
+
+using namespace mlu;
+
+extern "C" {
+
+int mlu_dsgesv_ir_workspace(int n, int nrhs, size_t* bytes) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (!bytes) return -3;
+  *bytes = ir_layout(n, nrhs).total;
+  return 0;
+}
+
+int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, const double* dB, int ldb, double* dX,
+                  int ldx, int precision, double tol, int max_iter, int variant, int nb, int nb_inner,
+                  int32_t* d_ipiv, int32_t* d_info, int32_t* d_iters, double* d_berr, void* d_work,
+                  size_t work_bytes) {
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (n > 0 && !dA) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && nrhs > 0 && !dB) return -6;
+  if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
+  if (n > 0 && nrhs > 0 && !dX) return -8;
+  if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32) return -10;
+  if (!(tol >= 0.0)) return -11;
+  if (max_iter < 0) return -12;
+  if (variant < MLU_RL || variant > MLU_LA) return -13;
+  if (nb < 1) return -14;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -15;
+  if (n > 0 && !d_ipiv) return -16;
+  if (!d_info) return -17;
+  if (!d_iters) return -18;
+  if (!d_berr) return -19;
+  if (!d_work) return -20;
+  const IrLayout L = ir_layout(n, nrhs);
+  if (work_bytes < L.total) return -21;
+  if (n > kPanelMaxRows) return -2;
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(d_work);
+  double* LU = reinterpret_cast<double*>(base + L.lu);
+  double* R = reinterpret_cast<double*>(base + L.r);
+  double* T = reinterpret_cast<double*>(base + L.t);
+  double* Linv = reinterpret_cast<double*>(base + L.linv);
+  double* Uinv = reinterpret_cast<double*>(base + L.uinv);
+  IrState* st = reinterpret_cast<IrState*>(base + L.state);
+  unsigned long long* bnorm = reinterpret_cast<unsigned long long*>(base + L.norms);
+  unsigned long long* xnorm = bnorm + nrhs;
+  unsigned long long* rnorm = xnorm + nrhs;
+  const int32_t* done = &st->done;
+
+  if (zero_bytes(s, d_iters, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
+  if (zero_bytes(s, d_berr, sizeof(double)) != hipSuccess) return MLU_ERR_HIP;
+  if (n == 0 || nrhs == 0) return zero_bytes(s, d_info, sizeof(int32_t)) == hipSuccess ? 0 : MLU_ERR_HIP;
+  if (zero_bytes(s, base + L.state, L.total - L.state) != hipSuccess) return MLU_ERR_HIP;
+
+  const unsigned g2 = grid_for((size_t)n * n), gr = grid_for((size_t)n * nrhs), gw = (unsigned)((n + 3) / 4);
+  // LU := A, factor with the low-precision trailing products
+  hipLaunchKernelGGL(k_ir_copy, dim3(g2), dim3(256), 0, s, n, n, dA, lda, LU, n, nullptr);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, precision, nullptr, 0, -1,
+                             d_work, work_bytes, 0);
+  if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
+  // inverses of the factors' 256 x 256 diagonal blocks (the solves below are
+  // then GEMVs), the norms of A and B, then x := (LU)^-1 P b
+  const unsigned gi = grid_for((size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock);
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Linv);
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Uinv);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, true, true, n, LU, n, Linv) != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, false, false, n, LU, n, Uinv) != hipSuccess) return MLU_ERR_HIP;
+  hipLaunchKernelGGL(k_ir_anorm, dim3(gw), dim3(256), 0, s, n, dA, lda, &st->anorm);
+  hipLaunchKernelGGL(k_ir_colmax, dim3(gr), dim3(256), 0, s, n, nrhs, dB, ldb, bnorm, nullptr);
+  hipLaunchKernelGGL(k_ir_copy, dim3(gr), dim3(256), 0, s, n, nrhs, dB, ldb, dX, ldx, nullptr);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, Linv, Uinv, dX, ldx, T, nullptr) != hipSuccess) return MLU_ERR_HIP;
+  // refinement: residual and stop test, then a correction, until converged
+  for (int it = 0; it <= max_iter; ++it) {
+    if (gemv(s, n, n, nrhs, dA, lda, dX, ldx, dB, ldb, R, nrhs, done) != hipSuccess) return MLU_ERR_HIP;
+    hipLaunchKernelGGL(k_ir_colmax, dim3(gr), dim3(256), 0, s, n, nrhs, R, nrhs, rnorm, done);
+    hipLaunchKernelGGL(k_ir_colmax, dim3(gr), dim3(256), 0, s, n, nrhs, dX, ldx, xnorm, done);
+    hipLaunchKernelGGL(k_ir_check, dim3(1), dim3(64), 0, s, nrhs, st, bnorm, xnorm, rnorm, tol, it, max_iter,
+                       d_iters, d_berr);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    if (it == max_iter) break;
+    if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, Linv, Uinv, R, nrhs, T, done) != hipSuccess) return MLU_ERR_HIP;
+    hipLaunchKernelGGL(k_ir_axpy, dim3(gr), dim3(256), 0, s, n, nrhs, R, nrhs, dX, ldx, done);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -19,7 +19,8 @@ constexpr int kThreads = 256;
 
 __global__ __launch_bounds__(kThreads) void k_laswp(double* __restrict__ A, int lda, int m, int k1, int k2,
                                                     const int32_t* __restrict__ ipiv, int ca0, int ca1,
-                                                    int cb0, int cb1, int32_t* __restrict__ info) {
+                                                    int cb0, int cb1, int32_t* __restrict__ info, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;   // a flag the caller raised on the device
   __shared__ int s_piv[kMaxSteps];
   __shared__ int s_slot[kMaxSteps];
   __shared__ int s_label[2 * kMaxSteps];
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_laswp(double* __restrict__ A, int 
 }  // namespace
 
 hipError_t laswp(hipStream_t s, double* A, int lda, int m, int k1, int k2, const int32_t* ipiv, int ca0,
-                 int ca1, int cb0, int cb1, int32_t* info) {
+                 int ca1, int cb0, int cb1, int32_t* info, const int32_t* skip) {
   if (ca1 < ca0) ca1 = ca0;
   if (cb1 < cb0) cb1 = cb0;
   const int ntot = (ca1 - ca0) + (cb1 - cb0);
@@ -104,7 +105,7 @@ hipError_t laswp(hipStream_t s, double* A, int lda, int m, int k1, int k2, const
   for (int a = k1; a < k2; a += kMaxSteps) {
     const int b = (k2 - a) < kMaxSteps ? k2 : a + kMaxSteps;
     hipLaunchKernelGGL(k_laswp, dim3(grid), dim3(kThreads), 0, s, A, lda, m, a, b, ipiv, ca0, ca1, cb0, cb1,
-                       info);
+                       info, skip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -64,10 +64,20 @@ size_t workspace_bytes();
 // All take row-major operands; element (i, j) of X is X[i*ldx + j].
 
 // C := C - A B   (A m x k, B k x n, C m x n).  `trailing` marks the outer
-// trailing updates (RL3, PF2, RU2): same kernel body, own kernel name, and
-// event-timed while a trace is active.
+// trailing updates (RL3, PF2, RU2, LL2): same kernel body, own kernel name.
+// Precision of the product in the outer trailing updates (the mixed-precision
+// factorization): the operands are rounded to it, the product accumulated in
+// it, and C stays FP64.
+constexpr int kPrecF64 = 0;
+constexpr int kPrecF32 = 1;
+
+// `trailing` selects the trailing-update kernel (and allows prec = kPrecF32);
+// `traced` lets a trailing launch record events while a trace is active.
+// `skip` (device flag, may be null; generic kernel only): when it reads
+// nonzero the launch does nothing.
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda,
-                       const double* B, int ldb, double* C, int ldc, bool trailing = false);
+                       const double* B, int ldb, double* C, int ldc, bool trailing = false,
+                       int prec = kPrecF64, bool traced = true, const int32_t* skip = nullptr);
 // The same update as a persistent kernel fed by the tile queues of one slot
 // (`q`: kXcd counters kQueueStride words apart, zero before the first launch
 // that uses them).  Each workgroup takes tiles from the queue of its own XCD,
@@ -78,7 +88,8 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 // tiles).  `clear` (may be null): kXcd counters that workgroup 0 zeroes first.
 // `grid` 0 = two workgroups per CU.
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
-                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced);
+                      double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
+                      int prec = kPrecF64);
 hipError_t trace_begin(int capacity);
 hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 
@@ -98,12 +109,26 @@ hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int ro
 // Apply interchanges ipiv[k1 .. k2) (1-based values, each >= its own index and
 // < m) to columns [ca0, ca1) and [cb0, cb1) of the m-row matrix A.
 hipError_t laswp(hipStream_t s, double* A, int lda, int m, int k1, int k2,
-                 const int32_t* ipiv, int ca0, int ca1, int cb0, int cb1, int32_t* info);
+                 const int32_t* ipiv, int ca0, int ca1, int cb0, int cb1, int32_t* info,
+                 const int32_t* skip = nullptr);
 
 // B := T^{-1} B with T (nr x nr) lower/upper, unit/non-unit, B nr x ncols.
 hipError_t trsm_left(hipStream_t s, bool lower, bool unit, int nr, int ncols,
-                     const double* T, int ldt, double* B, int ldb);
+                     const double* T, int ldt, double* B, int ldb, const int32_t* skip = nullptr);
+
+// Inverses of the 256 x 256 diagonal blocks of the triangle of T (n x n):
+// Inv holds ceil(n/256) blocks of 256 x 256 (leading dimension 256), which
+// must hold identities (the leading nr x nr of each) on entry.
+constexpr int kInvBlock = 256;
+hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv);
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes);
+
+// Argument checks and the whole factorization of mlu_dgetrf / mlu_dsgetrf
+// (C-ABI return codes; `sh` shifts the numbers of arguments after
+// `precision`).
+int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
+                void* d_work, size_t work_bytes, int sh);
 
 }  // namespace mlu

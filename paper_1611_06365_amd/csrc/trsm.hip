@@ -22,9 +22,23 @@ constexpr int kCols = 32;      // columns of B per workgroup
 constexpr int kPitch = kCols + 4;
 constexpr int kDiag = 16;      // diagonal block
 
+// Batched form (gridDim.y > 1, n_total > 0): triangle y is the diagonal block
+// of rows/columns [y kRows, min((y+1) kRows, n_total)) of T, solved against its
+// own square B block at B + y b_stride (the inverses of the diagonal blocks
+// when B holds identities).
 template <bool LOWER, bool UNIT>
 __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const double* __restrict__ T, int ldt,
-                                                  double* __restrict__ B, int ldb) {
+                                                  double* __restrict__ B, int ldb,
+                                                  const int32_t* __restrict__ skip, int n_total,
+                                                  long long b_stride) {
+  if (skip != nullptr && *skip != 0) return;   // a flag the caller raised on the device
+  if (n_total > 0) {
+    const int y = blockIdx.y;
+    nr = min(kRows, n_total - y * kRows);
+    ncols = nr;
+    T += (size_t)y * kRows * ((size_t)ldt + 1);
+    B += (size_t)y * (size_t)b_stride;
+  }
   __shared__ __attribute__((aligned(16))) double X[kRows * kPitch];
   __shared__ double Td[kDiag][kDiag + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -127,40 +141,58 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
 }
 
 hipError_t solve_block(hipStream_t s, bool lower, bool unit, int nr, int ncols, const double* T, int ldt,
-                       double* B, int ldb) {
+                       double* B, int ldb, const int32_t* skip) {
   const dim3 grid((ncols + kCols - 1) / kCols), block(256);
-  if (lower && unit) hipLaunchKernelGGL((k_trsm_lds<true, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else if (lower) hipLaunchKernelGGL((k_trsm_lds<true, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else if (unit) hipLaunchKernelGGL((k_trsm_lds<false, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
-  else hipLaunchKernelGGL((k_trsm_lds<false, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb);
+  if (lower && unit) hipLaunchKernelGGL((k_trsm_lds<true, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb, skip, 0, 0LL);
+  else if (lower) hipLaunchKernelGGL((k_trsm_lds<true, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb, skip, 0, 0LL);
+  else if (unit) hipLaunchKernelGGL((k_trsm_lds<false, true>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb, skip, 0, 0LL);
+  else hipLaunchKernelGGL((k_trsm_lds<false, false>), grid, block, 0, s, nr, ncols, T, ldt, B, ldb, skip, 0, 0LL);
   return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv) {
+  if (n <= 0) return hipSuccess;
+  const int nblk = (n + kRows - 1) / kRows;
+  const dim3 grid(kRows / kCols, nblk), block(256);
+  const long long stride = (long long)kRows * kRows;
+  if (lower && unit)
+    hipLaunchKernelGGL((k_trsm_lds<true, true>), grid, block, 0, s, 0, 0, T, ldt, Inv, kRows, nullptr, n, stride);
+  else if (lower)
+    hipLaunchKernelGGL((k_trsm_lds<true, false>), grid, block, 0, s, 0, 0, T, ldt, Inv, kRows, nullptr, n, stride);
+  else if (unit)
+    hipLaunchKernelGGL((k_trsm_lds<false, true>), grid, block, 0, s, 0, 0, T, ldt, Inv, kRows, nullptr, n, stride);
+  else
+    hipLaunchKernelGGL((k_trsm_lds<false, false>), grid, block, 0, s, 0, 0, T, ldt, Inv, kRows, nullptr, n, stride);
+  return hipGetLastError();
+}
+
 hipError_t trsm_left(hipStream_t s, bool lower, bool unit, int nr, int ncols, const double* T, int ldt,
-                     double* B, int ldb) {
+                     double* B, int ldb, const int32_t* skip) {
   if (nr <= 0 || ncols <= 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (lower) {
     for (int r0 = 0; r0 < nr; r0 += kRows) {
       const int rb = nr - r0 < kRows ? nr - r0 : kRows;
-      e = solve_block(s, true, unit, rb, ncols, T + (size_t)r0 * ldt + r0, ldt, B + (size_t)r0 * ldb, ldb);
+      e = solve_block(s, true, unit, rb, ncols, T + (size_t)r0 * ldt + r0, ldt, B + (size_t)r0 * ldb, ldb, skip);
       if (e != hipSuccess) return e;
       const int rest = nr - r0 - rb;
       if (rest > 0) {
         e = gemm_update(s, rest, ncols, rb, T + (size_t)(r0 + rb) * ldt + r0, ldt, B + (size_t)r0 * ldb, ldb,
-                        B + (size_t)(r0 + rb) * ldb, ldb);
+                        B + (size_t)(r0 + rb) * ldb, ldb, false, kPrecF64, true, skip);
         if (e != hipSuccess) return e;
       }
     }
   } else {
     for (int r1 = nr; r1 > 0; r1 -= kRows) {
       const int r0 = r1 - kRows > 0 ? r1 - kRows : 0;
-      e = solve_block(s, false, unit, r1 - r0, ncols, T + (size_t)r0 * ldt + r0, ldt, B + (size_t)r0 * ldb, ldb);
+      e = solve_block(s, false, unit, r1 - r0, ncols, T + (size_t)r0 * ldt + r0, ldt, B + (size_t)r0 * ldb, ldb,
+                      skip);
       if (e != hipSuccess) return e;
       if (r0 > 0) {
-        e = gemm_update(s, r0, ncols, r1 - r0, T + r0, ldt, B + (size_t)r0 * ldb, ldb, B, ldb);
+        e = gemm_update(s, r0, ncols, r1 - r0, T + r0, ldt, B + (size_t)r0 * ldb, ldb, B, ldb, false, kPrecF64, true,
+                        skip);
         if (e != hipSuccess) return e;
       }
     }

@@ -19,6 +19,8 @@ MLU_ERR_HIP = -1000
 MLU_INFO_SYNC_TIMEOUT = -999
 MLU_INFO_BAD_PIVOT = -998
 MLU_MAX_NB_INNER = 16
+MLU_PREC_FP64, MLU_PREC_FP32 = 0, 1
+PRECISION_IDS = {"fp64": MLU_PREC_FP64, "fp32": MLU_PREC_FP32}
 
 _vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
 
@@ -26,6 +28,10 @@ _SIGNATURES = {
     "mlu_version": ([], _i),
     "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
+    "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
+                       _vp, _vp, _sz], _i),
     "mlu_dtrsm": ([_vp, _c, _c, _i, _i, _vp, _i, _vp, _i], _i),
     "mlu_dgetrs": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i], _i),
     "mlu_dgemm_update": ([_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i], _i),
@@ -78,6 +84,24 @@ def mlu_dgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_s
                iters_limit, d_work, work_bytes) -> int:
     return _call("mlu_dgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_schedule,
                  n_schedule, iters_limit, d_work, work_bytes)
+
+
+def mlu_dsgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision, h_schedule, n_schedule,
+                iters_limit, d_work, work_bytes) -> int:
+    return _call("mlu_dsgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision,
+                 h_schedule, n_schedule, iters_limit, d_work, work_bytes)
+
+
+def mlu_dsgesv_ir_workspace(n, nrhs) -> tuple[int, int]:
+    out = _sz(0)
+    rc = _call("mlu_dsgesv_ir_workspace", n, nrhs, ctypes.byref(out))
+    return rc, out.value
+
+
+def mlu_dsgesv_ir(stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, max_iter, variant, nb, nb_inner,
+                  d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes) -> int:
+    return _call("mlu_dsgesv_ir", stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, max_iter, variant, nb,
+                 nb_inner, d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes)
 
 
 def mlu_dtrsm(stream, uplo, diag, m, nrhs, dT, ldt, dB, ldb) -> int:
@@ -153,10 +177,11 @@ def workspace(device=None):
 
 
 def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ipiv=None, info=None,
-          work=None, stream=None):
+          work=None, stream=None, precision="fp64"):
     """Factor A (m x n float64 CUDA tensor, row-major) in place; returns (ipiv, info) tensors.
 
-    No synchronization: read info after the stream has finished.
+    precision="fp32" calls mlu_dsgetrf (FP32 products in the outer trailing
+    updates).  No synchronization: read info after the stream has finished.
     """
     import torch
 
@@ -172,10 +197,48 @@ def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ip
         arr = (ctypes.c_int32 * len(schedule))(*[int(b) for b in schedule])
         sched, nsched = ctypes.cast(arr, ctypes.c_void_p), len(schedule)
     v = VARIANT_IDS[variant] if isinstance(variant, str) else int(variant)
-    rc = mlu_dgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
-                    nb_inner, sched, nsched, iters_limit, work.data_ptr(), work.numel())
-    check(rc, "mlu_dgetrf")
+    if precision == "fp64":
+        rc = mlu_dgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
+                        nb_inner, sched, nsched, iters_limit, work.data_ptr(), work.numel())
+        check(rc, "mlu_dgetrf")
+    else:
+        rc = mlu_dsgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
+                         nb_inner, PRECISION_IDS[precision], sched, nsched, iters_limit, work.data_ptr(),
+                         work.numel())
+        check(rc, "mlu_dsgetrf")
     return ipiv, info
+
+
+def gesv_ir(A, B, precision="fp32", tol=1e-13, max_iter=10, variant="la", nb=256, nb_inner=0, X=None, work=None,
+            stream=None):
+    """Solve A X = B by mixed-precision LU and FP64 refinement (mlu_dsgesv_ir).
+
+    Returns (X, ipiv, info, iters, berr); iters, berr and info are device
+    tensors, valid once the stream has finished.  A and B are not modified.
+    """
+    import torch
+
+    pa, lda = _rowmajor(A, "A")
+    pb, ldb = _rowmajor(B, "B")
+    n, nrhs = A.shape[0], B.shape[1]
+    if A.shape[1] != n or B.shape[0] != n:
+        raise ValueError("A must be n x n and B n x nrhs")
+    X = torch.empty_like(B) if X is None else X
+    px, ldx = _rowmajor(X, "X")
+    if work is None:
+        rc, nbytes = mlu_dsgesv_ir_workspace(n, nrhs)
+        check(rc, "mlu_dsgesv_ir_workspace")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    iters = torch.empty(1, dtype=torch.int32, device=A.device)
+    berr = torch.empty(1, dtype=torch.float64, device=A.device)
+    v = VARIANT_IDS[variant] if isinstance(variant, str) else int(variant)
+    rc = mlu_dsgesv_ir(_stream(stream), n, nrhs, pa, lda, pb, ldb, px, ldx, PRECISION_IDS[precision], tol,
+                       max_iter, v, nb, nb_inner, ipiv.data_ptr(), info.data_ptr(), iters.data_ptr(),
+                       berr.data_ptr(), work.data_ptr(), work.numel())
+    check(rc, "mlu_dsgesv_ir")
+    return X, ipiv, info, iters, berr
 
 
 def trsm(T, B, uplo="L", diag="U", stream=None):

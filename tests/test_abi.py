@@ -83,3 +83,35 @@ def test_other_argument_checks(lib):
     assert mlu.mlu_dlaswp(None, 4, 4, 1024, 4, 2, 1, 2048, None) == -7
     assert mlu.mlu_dgetf2_block(None, 32, 17, 1024, 17, 2048, 4096, 8192, 1 << 20) == -3
     assert mlu.mlu_dgetf2_block(None, 4, 8, 1024, 8, 2048, 4096, 8192, 1 << 20) == -3
+
+
+def test_mixed_argument_checks(lib):
+    import ctypes
+
+    from paper_1611_06365_amd import mlu
+
+    out = ctypes.c_size_t(0)
+    assert lib.mlu_dsgesv_ir_workspace(-1, 1, ctypes.byref(out)) == -1
+    assert lib.mlu_dsgesv_ir_workspace(4, -1, ctypes.byref(out)) == -2
+    assert lib.mlu_dsgesv_ir_workspace(4, 1, None) == -3
+    assert lib.mlu_dsgesv_ir_workspace(1000, 2, ctypes.byref(out)) == 0
+    assert out.value >= 1000 * 1000 * 8 + 1000 * 2 * 8
+    # argument checks return before anything is enqueued (no GPU needed)
+    args = dict(stream=None, n=4, nrhs=1, dA=8, lda=4, dB=8, ldb=1, dX=8, ldx=1, precision=1, tol=1e-13,
+                max_iter=5, variant=0, nb=2, nb_inner=0, d_ipiv=8, d_info=8, d_iters=8, d_berr=8, d_work=8,
+                work_bytes=1 << 40)
+    for key, bad, code in [("precision", 7, -10), ("tol", -1.0, -11), ("max_iter", -1, -12), ("variant", 9, -13),
+                           ("nb", 0, -14), ("nb_inner", 17, -15), ("work_bytes", 16, -21), ("lda", 3, -5)]:
+        kw = dict(args)
+        kw[key] = bad
+        assert mlu.mlu_dsgesv_ir(*kw.values()) == code, key
+    # mlu_dsgetrf: precision is argument 11, later arguments shift by one
+    g = dict(stream=None, m=4, n=4, dA=8, lda=4, d_ipiv=8, d_info=8, variant=0, nb=2, nb_inner=0, precision=1,
+             h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8, work_bytes=16)
+    kw = dict(g)
+    kw["precision"] = 5
+    assert mlu.mlu_dsgetrf(*kw.values()) == -11
+    assert mlu.mlu_dsgetrf(*g.values()) == -16      # workspace too small: argument 16
+    kw = dict(g)
+    kw["iters_limit"] = -2
+    assert mlu.mlu_dsgetrf(*kw.values()) == -14

@@ -1,0 +1,163 @@
+"""GPU tests of the mixed-precision path: mlu_dsgetrf (FP32 products in the
+outer trailing updates, everything else FP64) and mlu_dsgesv_ir (FP64
+iterative refinement on top of it).
+
+Bars:
+  * the FP32-product factors are those of a nearby matrix:
+    ||P A - L U||_F / ||A||_F <= 64 * n * 2^-24 ... kept simply as <= 5e-5 at
+    these orders (n <= 1024; the measured values are printed), and the pivots
+    are legal (|L| <= 1);
+  * precision=FP64 through mlu_dsgetrf is mlu_dgetrf, bit for bit;
+  * refinement: the backward error reported on the device is <= tol = 1e-13,
+    the same quantity recomputed here in FP64 from X agrees (<= 2e-13: the host
+    residual itself carries rounding of order sqrt(n) u ||A|| ||x||), and the
+    solution agrees with the FP64 oracle's (oracle getrf + getrs) to within
+    kappa * 1e-12 relative in the max norm: both are backward stable to about
+    1e-13, so their difference is bounded by kappa times that, with a margin.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs as G
+import oracle as O
+from paper_1611_06365_amd import mlu
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mlu.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def perm_rows(ipiv1, n):
+    perm = np.arange(n)
+    for c, p in enumerate(ipiv1.astype(np.int64) - 1):
+        perm[c], perm[p] = perm[p], perm[c]
+    return perm
+
+
+def backward_error(A, X, B):
+    R = B - A @ X
+    num = np.abs(R).max(axis=0)
+    den = np.abs(A).sum(axis=1).max() * np.abs(X).max(axis=0) + np.abs(B).max(axis=0)
+    return float((num / den).max())
+
+
+@pytest.mark.parametrize("variant", ["rl", "la", "ll"])
+@pytest.mark.parametrize("recipe,n", [("uniform", 600), ("spd", 1024), ("haar", 777)])
+def test_dsgetrf_fp32_factors(variant, recipe, n):
+    A = {"uniform": lambda: G.uniform01(n, seed=3), "spd": lambda: G.spd_bbt(n, seed=3),
+         "haar": lambda: G.haar_spectrum(n, 1e4, seed=3)}[recipe]()
+    dA = dev(A)
+    ipiv, info = mlu.getrf(dA, variant=variant, nb=128, precision="fp32")
+    F = host(dA)
+    assert int(host(info)[0]) == 0
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    res = np.linalg.norm(A[perm_rows(host(ipiv), n)] - L @ U) / np.linalg.norm(A)
+    print(f"dsgetrf fp32 {recipe} n={n} {variant}: residual {res:.2e}", flush=True)
+    assert res <= 5e-5
+    assert np.abs(np.tril(F, -1)).max() <= 1.0
+    assert res > 1e-12, "the trailing products do not look like FP32"
+
+
+def test_dsgetrf_fp64_is_dgetrf():
+    A = G.uniform01(513, seed=5)
+    d1, d2 = dev(A), dev(A)
+    p1, _ = mlu.getrf(d1, variant="la", nb=64)
+    p2, _ = mlu.getrf(d2, variant="la", nb=64, precision="fp64")
+    assert np.array_equal(host(p1), host(p2))
+    assert np.array_equal(host(d1), host(d2))
+
+
+_x64 = {}
+
+
+def oracle_solution(key, A, B):
+    if key not in _x64:
+        R = A.copy()
+        piv, info = O.getrf(R, "rl", nb=64)
+        assert info == 0
+        _x64[key] = O.getrs(R, piv, B)
+    return _x64[key]
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e5])
+@pytest.mark.parametrize("nrhs", [1, 3])
+@pytest.mark.parametrize("variant", ["rl", "la"])
+def test_gesv_ir_reaches_fp64_backward_error(cond, nrhs, variant):
+    n = 640
+    A = G.haar_spectrum(n, cond, seed=7)
+    B = G.gaussian_rhs(n, nrhs, seed=1)
+    dA, dB = dev(A), dev(B)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dA, dB, precision="fp32", tol=1e-13, max_iter=10, variant=variant,
+                                             nb=64)
+    Xh = host(X)
+    it, be = int(host(iters)[0]), float(host(berr)[0])
+    hb = backward_error(A, Xh, B)
+    X64 = oracle_solution((cond, nrhs), A, B)
+    fwd = np.abs(Xh - X64).max() / np.abs(X64).max()
+    print(f"gesv_ir fp32 cond={cond:g} nrhs={nrhs} {variant}: iters {it}, berr {be:.2e} (host {hb:.2e}), "
+          f"|x - x64|/|x64| {fwd:.2e}", flush=True)
+    assert int(host(info)[0]) == 0
+    assert np.array_equal(host(dA), A) and np.array_equal(host(dB), B), "A and B must not change"
+    assert 0 <= it <= 10
+    assert be <= 1e-13 and hb <= 2e-13
+    assert fwd <= cond * 1e-12
+
+
+def test_gesv_ir_fp64_needs_at_most_one_correction():
+    n = 500
+    A = G.uniform01(n, seed=9)
+    B = G.gaussian_rhs(n, 2, seed=2)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dev(A), dev(B), precision="fp64", tol=1e-13, max_iter=5, nb=64)
+    assert int(host(iters)[0]) in (0, 1) and float(host(berr)[0]) <= 1e-13
+    assert backward_error(A, host(X), B) <= 2e-13
+
+
+def test_gesv_ir_reports_no_convergence_consistently():
+    # kappa * u_32 >> 1: refinement on FP32-product factors is not expected to
+    # converge; whatever happens, the reported iteration count and backward
+    # error must agree with each other and with X
+    n = 400
+    A = G.haar_spectrum(n, 1e12, seed=4)
+    B = G.gaussian_rhs(n, 1, seed=3)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dev(A), dev(B), precision="fp32", tol=1e-15, max_iter=3, nb=64)
+    it, be = int(host(iters)[0]), float(host(berr)[0])
+    hb = backward_error(A, host(X), B)
+    print(f"gesv_ir cond=1e12 tol=1e-15: iters {it}, berr {be:.2e}, host {hb:.2e}", flush=True)
+    if it >= 0:
+        assert be <= 1e-15
+    else:
+        assert it == -1 and not (be <= 1e-15)
+    assert abs(hb - be) <= 0.5 * max(hb, be) + 1e-16
+
+
+def test_gesv_ir_zero_iterations_and_empty():
+    n = 64
+    A = G.spd_bbt(n, seed=1)
+    B = G.gaussian_rhs(n, 1, seed=1)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dev(A), dev(B), precision="fp32", tol=0.0, max_iter=0, nb=16)
+    # tol 0 is reached only by an exact residual; with max_iter 0 the answer is the first solve
+    assert int(host(iters)[0]) in (0, -1)
+    assert float(host(berr)[0]) == pytest.approx(backward_error(A, host(X), B), rel=0.5, abs=1e-17)
+    e = torch.zeros((0, 0), dtype=torch.float64, device=DEV)
+    b = torch.zeros((0, 1), dtype=torch.float64, device=DEV)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(e, b)
+    assert int(host(info)[0]) == 0 and int(host(iters)[0]) == 0 and float(host(berr)[0]) == 0.0
