@@ -29,7 +29,15 @@ if ROOT not in sys.path:
 
 METRIC = "GFLOP/s & %MFMA roofline at n=16384 (FP64 vs mixed+refine @1e-13); batched ops/s"
 FP64_PEAK_TFLOPS = 78.6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_trailing_n16384_traffic.md")
+# the traced launches: the outer trailing updates carrying nearly all flops
+KERNEL_LABEL = {
+    "la": "k_gemm_queue (RU2 as a persistent tile queue on the CUs the panel stream leaves, joined by the panel's "
+          "workgroups after PF3; the last iteration's k_gemm_trailing), v_mfma_f64_16x16x4f64",
+    "rl": "k_gemm_trailing (RL3), v_mfma_f64_16x16x4f64",
+    "ll": "k_gemm_trailing (LL2), v_mfma_f64_16x16x4f64",
+}
+TRAFFIC_KERNEL = {"la": "k_gemm_queue", "rl": "k_gemm_trailing", "ll": "k_gemm_trailing"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_queue_la_n16384_traffic.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1611_06365_amd", "csrc", "gemm.hip")
 
 
@@ -264,8 +272,8 @@ def main() -> int:
         achieved = per_launch_flops / per_launch_s / 1e12
         rec = traffic_record() if (n == 16384 and args.nb == 256 and args.variant == "la") else None
         traffic = None
-        if rec is not None:
-            traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+        if rec is not None:   # per traced launch: RU2 plus the helpers that join it
+            traffic = rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]
         roof = {
             "bound": "mfma",
             "achieved": round(achieved, 3),
@@ -273,7 +281,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
             "traffic": traffic,
-            "kernel": "k_gemm_trailing (RL3/PF2/RU2 trailing update, v_mfma_f64_16x16x4)",
+            "kernel": KERNEL_LABEL[args.variant],
             "launches": launches,
             "avg_launch_us": round(gemm_ms / launches * 1e3, 3),
             "algorithmic_flops_per_launch": per_launch_flops,
