@@ -107,6 +107,68 @@ def cpu_baseline(n: int):
     }
 
 
+def batched_section(args, dev):
+    """`args.batch` independent matrices, orders n ~ U{8..512} (seed 0), each
+    A = B B^T + n I with B ~ N(0, 1), factored by one mlu_?getrf_batched call
+    (FP64 and FP32), eager and as a captured graph replay; a pristine copy is
+    restored outside the timed region.  matrices/s and GFLOP/s = sum(2n^3/3)/t."""
+    import numpy as np
+    import torch
+
+    from paper_1611_06365_amd import mlu
+
+    rng = np.random.default_rng(0)
+    ns = rng.integers(8, 513, args.batch)
+    flops = float(np.sum(2.0 * ns.astype(np.float64) ** 3 / 3.0))
+    out = {"batch": int(args.batch), "n_range": [8, 512], "matrix": "A = B B^T + n I, B ~ N(0,1) per matrix",
+           "gflop": round(flops / 1e9, 3)}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        log(f"batched {name}: generating {args.batch} matrices")
+        offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
+        buf = torch.empty(int(offs[-1]), dtype=dt, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(1)
+        for n in np.unique(ns):
+            idx = np.nonzero(ns == n)[0]
+            b = torch.randn(len(idx), int(n), int(n), generator=g, dtype=torch.float64, device=dev)
+            a = torch.bmm(b, b.transpose(1, 2).contiguous())
+            a.diagonal(dim1=1, dim2=2).add_(float(n))
+            for t, i in enumerate(idx):
+                buf[int(offs[i]):int(offs[i + 1])].copy_(a[t].reshape(-1))
+            del a, b
+        pristine = buf.clone()
+        mats = [buf[int(offs[i]):int(offs[i + 1])].view(int(n), int(n)) for i, n in enumerate(ns)]
+        plan = mlu.BatchPlan(mats, max_n=512)
+        torch.cuda.synchronize()
+
+        def once(run):
+            buf.copy_(pristine)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1)
+
+        once(plan.run)
+        t_eager = min(once(plan.run) for _ in range(3))
+        bad = int((plan.info != 0).sum().item())
+        s = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                plan.run(stream=s)
+        t_graph = min(once(graph.replay) for _ in range(3))
+        out[name] = {"ms": round(t_eager, 3), "ms_graph_replay": round(t_graph, 3),
+                     "matrices_per_s": round(args.batch / (t_eager / 1e3), 1),
+                     "gflops": round(flops / (t_eager / 1e3) / 1e9, 1), "nonzero_info": bad}
+        log(f"batched {name}: {out[name]}")
+        del plan, mats, buf, pristine, graph
+        torch.cuda.empty_cache()
+    return out
+
+
 def mixed_section(args, dev):
     """FP32-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
     solve (the same entry point with FP64 products and no correction: getrf,
@@ -194,6 +256,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision + refinement measurement")
     ap.add_argument("--mixed-conds", default="1e2,1e5,1e8")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
+    ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -289,6 +353,10 @@ def main() -> int:
             "share_of_step_time": round(gemm_ms / ms, 4),
         }
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_section(args, dev)
+
     mixed = None
     if not args.no_mixed:
         del copies
@@ -327,6 +395,7 @@ def main() -> int:
         "frac_fp64_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
         "roofline": roof,
         "mixed": mixed,
+        "batched": batched,
         "cpu_baseline": cpu,
         "check": check,
     }

@@ -62,6 +62,9 @@ enum mlu_precision {
   MLU_PREC_FP32 = 1
 };
 
+/* Largest order of a matrix in the batched factorization. */
+#define MLU_BATCH_MAX_N 512
+
 /* Largest panel block held in registers by the diagonal-block kernel. */
 #define MLU_MAX_NB_INNER 16
 
@@ -156,6 +159,33 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
                   int ldx, int precision, double tol, int max_iter, int variant, int nb, int nb_inner,
                   int32_t *d_ipiv, int32_t *d_info, int32_t *d_iters, double *d_berr, void *d_work,
                   size_t work_bytes);
+
+/*
+ * Batched LU with partial pivoting of `batch` independent square matrices of
+ * different orders, in one persistent launch (Section 3 applied to each
+ * operand: blocked right-looking with an unblocked panel, Fig. "LU").
+ *  d_n      device int32[batch]: order of matrix i, 0 <= n_i <= max_n.
+ *  d_A      device array of batch device pointers: matrix i, row-major,
+ *           leading dimension d_lda[i] >= max(1, n_i); factored in place into
+ *           {L\U} as mlu_dgetrf.
+ *  d_ipiv   device array of batch device pointers: int32[n_i] interchanges of
+ *           matrix i (1-based, sequential, as mlu_dgetrf).
+ *  d_info   device int32[batch]: 0, j > 0 for the first exactly zero pivot
+ *           (factorization completed), or -1 if n_i or d_lda[i] is invalid
+ *           (the matrix is left untouched).
+ *  max_n    an upper bound on every n_i (<= MLU_BATCH_MAX_N).
+ *  d_work   mlu_getrf_batched_workspace(batch) bytes.
+ * Matrices are processed largest first (a device counting sort), one per
+ * 256-thread workgroup at a time from an atomic queue.  The call enqueues
+ * kernels only (no memset): it can be captured in a stream graph.
+ * Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
+ */
+int mlu_getrf_batched_workspace(int batch, size_t *bytes);
+int mlu_dgetrf_batched(void *stream, int batch, const int32_t *d_n, double *const *d_A, const int32_t *d_lda,
+                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, void *d_work, size_t work_bytes);
+/* The same in FP32 (float matrices). */
+int mlu_sgetrf_batched(void *stream, int batch, const int32_t *d_n, float *const *d_A, const int32_t *d_lda,
+                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, void *d_work, size_t work_bytes);
 
 /*
  * Triangular solve with several right-hand sides, left side, no transpose:

@@ -124,6 +124,11 @@ hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes);
 
+// batched LU: workspace (queue counter and the size-sorted order) and the
+// one-time raise of the kernels' LDS limit
+size_t batched_workspace_bytes(int batch);
+hipError_t batched_set_lds_limits();
+
 // Argument checks and the whole factorization of mlu_dgetrf / mlu_dsgetrf
 // (C-ABI return codes; `sh` shifts the numbers of arguments after
 // `precision`).

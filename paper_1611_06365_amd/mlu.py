@@ -32,6 +32,9 @@ _SIGNATURES = {
     "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
                        _vp, _vp, _sz], _i),
+    "mlu_getrf_batched_workspace": ([_i, ctypes.POINTER(_sz)], _i),
+    "mlu_dgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz], _i),
+    "mlu_sgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz], _i),
     "mlu_dtrsm": ([_vp, _c, _c, _i, _i, _vp, _i, _vp, _i], _i),
     "mlu_dgetrs": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i], _i),
     "mlu_dgemm_update": ([_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i], _i),
@@ -102,6 +105,20 @@ def mlu_dsgesv_ir(stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, ma
                   d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes) -> int:
     return _call("mlu_dsgesv_ir", stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, max_iter, variant, nb,
                  nb_inner, d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes)
+
+
+def mlu_getrf_batched_workspace(batch) -> tuple[int, int]:
+    out = _sz(0)
+    rc = _call("mlu_getrf_batched_workspace", batch, ctypes.byref(out))
+    return rc, out.value
+
+
+def mlu_dgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes) -> int:
+    return _call("mlu_dgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes)
+
+
+def mlu_sgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes) -> int:
+    return _call("mlu_sgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes)
 
 
 def mlu_dtrsm(stream, uplo, diag, m, nrhs, dT, ldt, dB, ldb) -> int:
@@ -285,3 +302,66 @@ def getf2_block(A, ipiv=None, info=None, work=None, stream=None):
                           work.data_ptr(), work.numel())
     check(rc, "mlu_dgetf2_block")
     return ipiv, info
+
+
+MLU_BATCH_MAX_N = 512
+
+
+class BatchPlan:
+    """Device arrays describing a batch of square matrices for mlu_?getrf_batched:
+    orders, matrix pointers, leading dimensions, one int32 interchange buffer
+    (with per-matrix pointers into it), info and the workspace.  Built once;
+    the matrices it points to are factored in place by `run`."""
+
+    def __init__(self, mats, max_n=None):
+        import torch
+
+        if not mats:
+            raise ValueError("empty batch")
+        dt = mats[0].dtype
+        if dt not in (torch.float64, torch.float32):
+            raise ValueError("matrices must be float64 or float32")
+        dev = mats[0].device
+        ns, ptrs, ldas = [], [], []
+        for m in mats:
+            if m.dtype != dt or m.device != dev or m.dim() != 2 or m.shape[0] != m.shape[1] or (
+                    m.numel() and m.stride(1) != 1):
+                raise ValueError("every matrix must be a square row-major tensor of the batch's dtype and device")
+            ns.append(int(m.shape[0]))
+            ptrs.append(int(m.data_ptr()))
+            ldas.append(max(1, int(m.stride(0)) if m.numel() else 1))
+        self.dtype, self.batch = dt, len(mats)
+        self.max_n = max(ns) if max_n is None else int(max_n)
+        offs = [0]
+        for n in ns:
+            offs.append(offs[-1] + max(n, 1))
+        self.ipiv = torch.empty(offs[-1], dtype=torch.int32, device=dev)
+        base = self.ipiv.data_ptr()
+        self.offsets = offs
+        self.d_n = torch.tensor(ns, dtype=torch.int32, device=dev)
+        self.d_A = torch.tensor(ptrs, dtype=torch.int64, device=dev)
+        self.d_lda = torch.tensor(ldas, dtype=torch.int32, device=dev)
+        self.d_ipiv = torch.tensor([base + 4 * o for o in offs[:-1]], dtype=torch.int64, device=dev)
+        self.info = torch.empty(len(mats), dtype=torch.int32, device=dev)
+        rc, nbytes = mlu_getrf_batched_workspace(len(mats))
+        check(rc, "mlu_getrf_batched_workspace")
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        import torch
+
+        fn = mlu_dgetrf_batched if self.dtype == torch.float64 else mlu_sgetrf_batched
+        rc = fn(_stream(stream), self.batch, self.d_n.data_ptr(), self.d_A.data_ptr(), self.d_lda.data_ptr(),
+                self.d_ipiv.data_ptr(), self.info.data_ptr(), self.max_n, self.work.data_ptr(), self.work.numel())
+        check(rc, "mlu_getrf_batched")
+
+    def pivots(self, i):
+        return self.ipiv[self.offsets[i]:self.offsets[i + 1]]
+
+
+def getrf_batched(mats, max_n=None, stream=None):
+    """Factor every matrix of the list in place; returns the BatchPlan (its
+    `info` and `pivots(i)` are valid once the stream has finished)."""
+    plan = BatchPlan(mats, max_n)
+    plan.run(stream)
+    return plan

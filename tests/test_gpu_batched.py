@@ -1,0 +1,138 @@
+"""GPU parity of the batched LU (mlu_dgetrf_batched / mlu_sgetrf_batched):
+every matrix of a mixed-size batch against the oracle, on the same inputs.
+
+Bars (FP64): pivots identical, factors within 1e-12 * max|F_oracle| (orders up
+to 300; rounding order differs), residual ||P A - L U||_F / ||A||_F <= 1e-13;
+known-answer matrices bit-exact; info codes exact.  FP32: residual
+<= 1e-5 (about 64 n u_32 at these orders) and legal pivots (|L| <= 1).
+Graph capture: replays of a captured call reproduce the eager result bit for
+bit, with eager work and synchronizations between the replays.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs as G
+import oracle as O
+from oracle import invariants as I
+from paper_1611_06365_amd import mlu
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mlu.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+SIZES = [1, 2, 3, 7, 16, 31, 32, 33, 47, 63, 64, 65, 96, 100, 127, 128, 129, 160, 200, 255, 256, 257, 300]
+
+
+def make_batch(seed=0):
+    rng = np.random.default_rng(seed)
+    mats = []
+    for i, n in enumerate(SIZES + list(rng.integers(1, 150, 40))):
+        n = int(n)
+        mats.append(G.uniform01(n, seed=100 + i) if i % 3 else G.spd_bbt(n, seed=100 + i))
+    return mats
+
+
+def test_batched_fp64_against_oracle():
+    mats = make_batch()
+    dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
+    plan = mlu.getrf_batched(dmats)
+    info = host(plan.info)
+    for i, (a, d) in enumerate(zip(mats, dmats)):
+        n = a.shape[0]
+        F = host(d)
+        piv = (host(plan.pivots(i)) - 1).tolist()
+        R = a.copy()
+        opiv, oinfo = O.getrf(R, "rl", nb=32)
+        assert info[i] == oinfo == 0, i
+        assert piv == opiv, (i, n)
+        assert np.abs(F - R).max() <= 1e-12 * max(1.0, np.abs(R).max()), (i, n)
+        assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-13, (i, n)
+
+
+def test_batched_known_answer_and_zero_pivot():
+    mats, expect = [], []
+    for i, n in enumerate([5, 33, 64, 97, 130]):
+        A, perm, L, U = G.known_answer(n, n, seed=7 + i)
+        mats.append(A)
+        expect.append(0)
+    for col in (0, 17, 40):
+        mats.append(G.zero_column(48, seed=4, col=col))
+        expect.append(col + 1)
+    dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
+    plan = mlu.getrf_batched(dmats)
+    info = host(plan.info)
+    for i, (a, d) in enumerate(zip(mats, dmats)):
+        R = a.copy()
+        opiv, oinfo = O.getrf(R, "rl", nb=32)
+        assert info[i] == oinfo == expect[i]
+        assert (host(plan.pivots(i)) - 1).tolist() == opiv
+        assert np.array_equal(host(d), R), i
+
+
+def test_batched_invalid_entries_are_reported_and_untouched():
+    ok = torch.from_numpy(G.uniform01(40, seed=1)).to(DEV)
+    big = torch.from_numpy(G.uniform01(70, seed=2)).to(DEV)
+    big0 = big.clone()
+    empty = torch.zeros((0, 0), dtype=torch.float64, device=DEV)
+    plan = mlu.BatchPlan([ok, big, empty], max_n=64)   # 70 > max_n
+    plan.run()
+    info = host(plan.info)
+    assert info.tolist() == [0, -1, 0]
+    assert torch.equal(big, big0)
+
+
+def test_batched_fp32():
+    mats = make_batch(seed=3)[:40]
+    dmats = [torch.from_numpy(a.astype(np.float32)).to(DEV) for a in mats]
+    plan = mlu.getrf_batched(dmats)
+    info = host(plan.info)
+    for i, (a, d) in enumerate(zip(mats, dmats)):
+        a32 = a.astype(np.float32).astype(np.float64)
+        F = host(d).astype(np.float64)
+        piv = (host(plan.pivots(i)) - 1).tolist()
+        assert info[i] == 0
+        res = I.postcondition(a32, F, piv)["rel_frob"]
+        assert res <= 1e-5, (i, a.shape[0], res)
+        assert np.abs(np.tril(F, -1)).max() <= 1.0
+
+
+def test_batched_graph_replays_match_eager():
+    mats = make_batch(seed=5)[:30]
+    pristine = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
+    work = [p.clone() for p in pristine]
+    plan = mlu.BatchPlan(work)
+    plan.run()                      # eager reference (also raises the LDS limit outside capture)
+    ref = [w.clone() for w in work]
+    ref_piv = plan.ipiv.clone()
+    for w, p in zip(work, pristine):
+        w.copy_(p)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.run(stream=s)
+    for rep in range(3):
+        for w, p in zip(work, pristine):
+            w.copy_(p)
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device=DEV) * rep).sum().item()   # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(plan.ipiv, ref_piv), rep
+        for w, r in zip(work, ref):
+            assert torch.equal(w, r), rep
