@@ -111,7 +111,9 @@ def batched_section(args, dev):
     """`args.batch` independent matrices, orders n ~ U{8..512} (seed 0), each
     A = B B^T + n I with B ~ N(0, 1), factored by one mlu_?getrf_batched call
     (FP64 and FP32), eager and as a captured graph replay; a pristine copy is
-    restored outside the timed region.  matrices/s and GFLOP/s = sum(2n^3/3)/t."""
+    restored outside the timed region.  The panel width is chosen first by
+    mlu.tune_batched (each candidate timed on copies).  matrices/s and
+    GFLOP/s = sum(2n^3/3)/t."""
     import numpy as np
     import torch
 
@@ -138,7 +140,10 @@ def batched_section(args, dev):
             del a, b
         pristine = buf.clone()
         mats = [buf[int(offs[i]):int(offs[i + 1])].view(int(n), int(n)) for i, n in enumerate(ns)]
-        plan = mlu.BatchPlan(mats, max_n=512)
+        torch.cuda.synchronize()
+        nb, tune_ms = mlu.tune_batched(mats, max_n=512)
+        log(f"batched {name}: panel width by timing {tune_ms} -> {nb}")
+        plan = mlu.BatchPlan(mats, max_n=512, nb=nb)
         torch.cuda.synchronize()
 
         def once(run):
@@ -160,7 +165,8 @@ def batched_section(args, dev):
             with torch.cuda.graph(graph, stream=s):
                 plan.run(stream=s)
         t_graph = min(once(graph.replay) for _ in range(3))
-        out[name] = {"ms": round(t_eager, 3), "ms_graph_replay": round(t_graph, 3),
+        out[name] = {"nb": nb, "tuning_ms": {str(k): round(v, 3) for k, v in tune_ms.items()},
+                     "ms": round(t_eager, 3), "ms_graph_replay": round(t_graph, 3),
                      "matrices_per_s": round(args.batch / (t_eager / 1e3), 1),
                      "gflops": round(flops / (t_eager / 1e3) / 1e9, 1), "nonzero_info": bad}
         log(f"batched {name}: {out[name]}")

@@ -174,18 +174,22 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
  *           (factorization completed), or -1 if n_i or d_lda[i] is invalid
  *           (the matrix is left untouched).
  *  max_n    an upper bound on every n_i (<= MLU_BATCH_MAX_N).
+ *  nb       panel width: 16 or 32 (a tuning choice, results differ only in
+ *           rounding), 0 for the default (16).
  *  d_work   mlu_getrf_batched_workspace(batch) bytes.
  * Matrices are processed largest first (a device counting sort), one per
- * 256-thread workgroup at a time from an atomic queue.  The call enqueues
+ * 512-thread workgroup at a time from an atomic queue.  The call enqueues
  * kernels only (no memset): it can be captured in a stream graph.
  * Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
  */
 int mlu_getrf_batched_workspace(int batch, size_t *bytes);
 int mlu_dgetrf_batched(void *stream, int batch, const int32_t *d_n, double *const *d_A, const int32_t *d_lda,
-                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, void *d_work, size_t work_bytes);
+                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, int nb, void *d_work,
+                       size_t work_bytes);
 /* The same in FP32 (float matrices). */
 int mlu_sgetrf_batched(void *stream, int batch, const int32_t *d_n, float *const *d_A, const int32_t *d_lda,
-                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, void *d_work, size_t work_bytes);
+                       int32_t *const *d_ipiv, int32_t *d_info, int max_n, int nb, void *d_work,
+                       size_t work_bytes);
 
 /*
  * Triangular solve with several right-hand sides, left side, no transpose:

@@ -5,19 +5,20 @@
 //
 // A device counting sort orders the matrices by decreasing order (the largest
 // first, so that the launch's tail holds small ones); a persistent grid of
-// 256-thread workgroups takes matrices from an atomic queue in that order.
-// One workgroup factors one matrix at a time, kNB columns per step:
-//   1. the (n - j) x kNB panel is loaded into LDS and factored there with
+// 512-thread workgroups takes matrices from an atomic queue in that order.
+// One workgroup factors one matrix at a time, NB (16 or 32) columns per step:
+//   1. the (n - j) x NB panel is loaded into LDS and factored there with
 //      partial pivoting (argmax by wave reduction, first row on ties; the
 //      swap, the scaling and the rank-1 update in LDS);
 //   2. each thread owns columns outside the panel and applies the panel's
 //      interchanges to them in order (no barrier needed);
-//   3. A12 is staged into LDS 64 columns at a time, solved there with the
-//      panel's unit lower triangle (A12 := trilu(A11)^-1 A12, one column per
-//      thread), written back as U12, and the trailing matrix is updated with
-//      the chunk, A22 -= A21 U12, 4 x 4 register tiles of FMAs with A21 read
-//      from the LDS panel.  (FP64 vector and matrix peaks are equal on this part; the
-//      operands are small and irregular, so the update stays on the VALU.)
+//   3. A12 is staged into LDS 64 columns at a time and multiplied by the
+//      inverse of the panel's unit lower triangle (computed once per panel),
+//      U12 := trilu(A11)^-1 A12, written back, and the trailing matrix is
+//      updated with the chunk, A22 -= A21 U12, 4 x 4 register tiles of FMAs
+//      with A21 read from the LDS panel.  (FP64 vector and matrix peaks are
+//      equal on this part; the operands are small and irregular, so the
+//      update stays on the VALU.)
 // Matrices are row-major (element (i, j) at A[i*lda + j]), in place.
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
@@ -28,21 +29,44 @@
 namespace mlu {
 namespace {
 
-constexpr int kBT = 256;           // threads per workgroup
-constexpr int kNB = 32;            // panel width
-constexpr int kNBp = kNB + 1;      // LDS pitch of the panel
+constexpr int kBT = 512;           // threads per workgroup: one panel row each
 constexpr int kUC = 64;            // A12 columns staged per chunk
 constexpr int kMaxN = MLU_BATCH_MAX_N;
+constexpr int kBatchDefaultNB = 16;   // panel width when the caller passes 0
 
-template <typename T>
+template <typename T, int NB>
 struct BatchLds {
-  T P[kMaxN * kNBp];       // the panel, rows 0 .. n-j-1
-  T U[kNB * kUC];          // A12 chunk
+  static constexpr int kP = NB + 1;   // LDS pitch of the panel
+  T P[kMaxN * kP];         // the factored panel (L11\U11 over L21), rows 0 .. n-j-1
+  T U[NB * kUC];           // U12 chunk
+  T prow[NB];              // the pivot row of the current column
   T wv[kBT / kWave];
   int wr[kBT / kWave];
-  int piv[kNB];
-  int p;
+  int src[kMaxN];          // after the panel: the row now at position r came from src[r]
+  int piv[NB];
   int item;
+};
+
+// v_mfma 16 x 16 x 4 in the operand type: A fragment element (li, k), B
+// fragment element (k, li) with k chosen by lane >> 4; the four outputs of a
+// lane are rows row_of(lq, r) of column li.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row_of(int lq, int r) { return lq + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row_of(int lq, int r) { return 4 * lq + r; }
 };
 
 template <typename T>
@@ -58,135 +82,172 @@ __device__ __forceinline__ void wave_argmax_t(T& v, int& r) {
   }
 }
 
-template <typename T>
-__device__ void factor_one(int n, T* __restrict__ A, int lda, int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
-                           BatchLds<T>& L) {
+template <typename T, int NB>
+__device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, int32_t* __restrict__ ipiv,
+                                           int32_t* __restrict__ info, BatchLds<T, NB>& L) {
+  constexpr int kP = BatchLds<T, NB>::kP;
+  static_assert(kMaxN == kBT, "one panel row per thread");
+  constexpr int kTG = kBT / kUC;     // threads per column in the solve for U12
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int zero_col = INT_MAX;
-  for (int j = 0; j < n; j += kNB) {
-    const int nb = min(kNB, n - j), rows = n - j;
-    // 1. panel -> LDS
-    for (int e = tid; e < rows * kNB; e += kBT) {
-      const int r = e / kNB, c = e % kNB;
-      L.P[r * kNBp + c] = c < nb ? A[(size_t)(j + r) * lda + j + c] : T(0);
+  for (int j = 0; j < n; j += NB) {
+    const int nb = min(NB, n - j), rows = n - j;
+    // 1. the panel in registers, one row per thread.  Rows are not moved
+    //    while the panel is factored: each thread keeps the position its row
+    //    has reached under the interchanges so far (pos) and whether it is
+    //    still below the diagonal (live); the search breaks ties by position.
+    const int r = tid;
+    T v[NB];
+    {
+      const bool own = r < rows;
+      const T* a = A + (size_t)(j + (own ? r : 0)) * lda + j;
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) v[cc] = (own && cc < nb) ? a[cc] : T(0);
+    }
+    int pos = r;
+    bool live = r < rows;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c < nb) {   // uniform: only the last panel is narrower
+        T bv = T(-1);
+        int bp = INT_MAX;
+        const T av = fabs(v[c]);
+        if (live && av > bv) {
+          bv = av;
+          bp = pos;
+        }
+        wave_argmax_t(bv, bp);
+        if (lane == 0) {
+          L.wv[wave] = bv;
+          L.wr[wave] = bp;
+        }
+        __syncthreads();
+        T pm = L.wv[0];
+        int p = L.wr[0];
+#pragma unroll
+        for (int w = 1; w < kBT / kWave; ++w)
+          if (L.wv[w] > pm || (L.wv[w] == pm && L.wr[w] < p)) {
+            pm = L.wv[w];
+            p = L.wr[w];
+          }
+        p = __builtin_amdgcn_readfirstlane(p);
+        if (p >= rows) p = c;   // no comparable entry (a column of NaNs): keep the row
+        if (tid == 0) L.piv[c] = p;
+        const bool me = live && pos == p;
+        if (me) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) L.prow[cc] = v[cc];
+        }
+        __syncthreads();
+        if (me) {   // the interchange of positions c and p
+          live = false;
+          pos = c;
+        } else if (live && pos == c) {
+          pos = p;
+        }
+        const T pv = L.prow[c];
+        if (pv == T(0)) {
+          if (j + c < zero_col) zero_col = j + c;   // same value in every thread
+        } else if (live) {
+          const T l = v[c] / pv;
+          v[c] = l;
+#pragma unroll
+          for (int cc = c + 1; cc < NB; ++cc) v[cc] -= l * L.prow[cc];
+        }
+      }
+    }
+    // the factored panel to its final rows, in global and in LDS (A21 and
+    // trilu(A11) for step 3); src[t] := the panel-start position of the row
+    // now at position t
+    if (r < rows) {
+      T* a = A + (size_t)(j + pos) * lda + j;
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) {
+        if (cc < nb) a[cc] = v[cc];
+        L.P[pos * kP + cc] = v[cc];
+      }
+      L.src[pos] = r;
     }
     __syncthreads();
-    for (int c = 0; c < nb; ++c) {
-      T bv = T(-1);
-      int br = INT_MAX;
-      for (int r = c + tid; r < rows; r += kBT) {
-        const T a = fabs(L.P[r * kNBp + c]);
-        if (a > bv) {   // rows visited in increasing order: the first maximum stays
-          bv = a;
-          br = r;
-        }
-      }
-      wave_argmax_t(bv, br);
-      if (lane == 0) {
-        L.wv[wave] = bv;
-        L.wr[wave] = br;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        T v = L.wv[0];
-        int r = L.wr[0];
-        for (int w = 1; w < kBT / kWave; ++w)
-          if (L.wv[w] > v || (L.wv[w] == v && L.wr[w] < r)) {
-            v = L.wv[w];
-            r = L.wr[w];
-          }
-        L.p = r;
-        L.piv[c] = r;
-      }
-      __syncthreads();
-      const int p = L.p;
-      if (p != c && tid < nb) {
-        const T t = L.P[c * kNBp + tid];
-        L.P[c * kNBp + tid] = L.P[p * kNBp + tid];
-        L.P[p * kNBp + tid] = t;
-      }
-      __syncthreads();
-      const T pv = L.P[c * kNBp + c];
-      if (pv == T(0)) {
-        if (j + c < zero_col) zero_col = j + c;   // same value in every thread
-      } else {
-        for (int r = c + 1 + tid; r < rows; r += kBT) {
-          const T l = L.P[r * kNBp + c] / pv;
-          L.P[r * kNBp + c] = l;
-          for (int cc = c + 1; cc < nb; ++cc) L.P[r * kNBp + cc] -= l * L.P[c * kNBp + cc];
-        }
-      }
-      __syncthreads();
-    }
-    // panel -> global, interchanges recorded
-    for (int e = tid; e < rows * kNB; e += kBT) {
-      const int r = e / kNB, c = e % kNB;
-      if (c < nb) A[(size_t)(j + r) * lda + j + c] = L.P[r * kNBp + c];
-    }
     if (tid < nb) ipiv[j + tid] = j + L.piv[tid] + 1;
-    // 2. columns outside the panel: the panel's interchanges, in order (a
-    //    thread owns its columns, so no barrier between the swaps)
-    for (int col = tid; col < n - nb; col += kBT) {
-      const int g = col < j ? col : col + nb;
-      for (int c = 0; c < nb; ++c) {
-        const int p = L.piv[c];
-        if (p != c) {
-          T* a = A + (size_t)(j + c) * lda + g;
-          T* b = A + (size_t)(j + p) * lda + g;
-          const T t = *a;
-          *a = *b;
-          *b = t;
+    // 2. the interchanges outside the panel, gathered: the row at position t
+    //    becomes the one from src[t] for t in {0..nb-1} and {piv[c]}; every
+    //    other row is unmoved.  A thread owns a column; all its loads are
+    //    issued before any of its stores (no order among the swaps remains).
+    bool any = false;
+    for (int c = 0; c < nb; ++c) any |= L.piv[c] != c;
+    if (any) {
+      for (int col = tid; col < n - nb; col += kBT) {
+        const int g = col < j ? col : col + nb;
+        T st[2 * NB];
+#pragma unroll
+        for (int k = 0; k < 2 * NB; ++k) {
+          const int t = k < NB ? (k < nb ? k : 0) : (k - NB < nb ? L.piv[k - NB] : 0);
+          st[k] = A[(size_t)(j + L.src[t]) * lda + g];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * NB; ++k) {
+          const int t = k < NB ? (k < nb ? k : 0) : (k - NB < nb ? L.piv[k - NB] : 0);
+          A[(size_t)(j + t) * lda + g] = st[k];   // every store to row t carries the same value
         }
       }
     }
-    __syncthreads();   // global writes visible inside the workgroup
-    // 3. per chunk of kUC right columns: A12 -> LDS, A12 := trilu(A11)^-1 A12
-    //    (one column per thread, in LDS), back to global as U12, then
-    //    A22 -= A21 U12 with the chunk
+    __syncthreads();   // P, and the interchanged columns, visible to the workgroup
+    // 3. per chunk of kUC right columns: U12 := trilu(A11)^-1 A12 (kTG
+    //    threads per column, forward substitution), then A22 -= A21 U12 on
+    //    the matrix cores, 16 x 16 blocks spread over the waves.  (Only a
+    //    full panel has right columns: nb == NB here.)
     const int R = rows - nb;
     for (int c0 = 0; c0 < R; c0 += kUC) {
       const int cw = min(kUC, R - c0);
-      for (int e = tid; e < kNB * kUC; e += kBT) {
-        const int k = e / kUC, c = e % kUC;
-        L.U[e] = (k < nb && c < cw) ? A[(size_t)(j + k) * lda + j + nb + c0 + c] : T(0);
-      }
-      __syncthreads();
-      if (tid < cw) {
-        for (int r = 1; r < nb; ++r) {
-          T v = L.U[r * kUC + tid];
-          for (int q = 0; q < r; ++q) v -= L.P[r * kNBp + q] * L.U[q * kUC + tid];
-          L.U[r * kUC + tid] = v;
-        }
-        for (int r = 1; r < nb; ++r) A[(size_t)(j + r) * lda + j + nb + c0 + tid] = L.U[r * kUC + tid];
-      }
-      __syncthreads();
-      const int tr = (R + 3) / 4, tc = (cw + 3) / 4;
-      for (int t = tid; t < tr * tc; t += kBT) {
-        const int r0 = (t / tc) * 4, cc0 = (t % tc) * 4;
-        T acc[4][4];
+      {
+        // thread (c, t) holds rows kTG * i + t of column c
+        const int c = tid / kTG, t = tid % kTG;
+        const bool ok = c < cw;
+        T* a = A + (size_t)j * lda + j + nb + c0 + c;
+        T x[NB / kTG];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NB / kTG; ++i) x[i] = ok ? a[(size_t)(kTG * i + t) * lda] : T(0);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[i][q] = T(0);
-        for (int k = 0; k < nb; ++k) {
-          T a[4], b[4];
+        for (int k = 0; k < NB - 1; ++k) {
+          const T xk = __shfl(x[k / kTG], (lane & ~(kTG - 1)) | (k % kTG));
 #pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = (r0 + i < R) ? L.P[(nb + r0 + i) * kNBp + k] : T(0);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) b[q] = L.U[k * kUC + cc0 + q];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[i][q] += a[i] * b[q];
+          for (int i = k / kTG; i < NB / kTG; ++i)
+            if (kTG * i + t > k) x[i] -= L.P[(kTG * i + t) * kP + k] * xk;
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NB / kTG; ++i) {
+          L.U[(kTG * i + t) * kUC + c] = x[i];
+          if (ok && kTG * i + t > 0) a[(size_t)(kTG * i + t) * lda] = x[i];
+        }
+      }
+      __syncthreads();
+      {
+        typedef typename Mfma<T>::acc_t acc_t;
+        const int li = lane & 15, lq = lane >> 4;
+        const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16, npair = nrb * nsb;
+        T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
+        for (int pp = wave; pp < npair; pp += kBT / kWave) {
+          const int rb = pp / nsb, cb = (pp - rb * nsb) * 16 + li;
+          const bool cok = cb < cw;
+          acc_t acc;
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (r0 + i < R && cc0 + q < cw) {
-              T* cp = A + (size_t)(j + nb + r0 + i) * lda + j + nb + c0 + cc0 + q;
-              *cp -= acc[i][q];
-            }
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+            acc[r] = (cok && row < R) ? C[(size_t)row * lda + cb] : T(0);
+          }
+          const int arow = nb + min(rb * 16 + li, R - 1);
+#pragma unroll
+          for (int s4 = 0; s4 < NB / 4; ++s4) {
+            const int k = 4 * s4 + lq;
+            acc = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + (cb & (kUC - 1))], acc);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+            if (cok && row < R) C[(size_t)row * lda + cb] = acc[r];
+          }
+        }
       }
       __syncthreads();
     }
@@ -221,13 +282,13 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int32_t* 
   for (int i = tid; i < batch; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
 }
 
-template <typename T>
+template <typename T, int NB>
 __global__ __launch_bounds__(kBT) void k_getrf_batched(int batch, const int32_t* __restrict__ d_n, T* const* d_A,
                                                        const int32_t* __restrict__ d_lda, int32_t* const* d_ipiv,
                                                        int32_t* __restrict__ d_info, int max_n,
                                                        const int32_t* __restrict__ order, unsigned* queue) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  BatchLds<T>& L = *reinterpret_cast<BatchLds<T>*>(smem);
+  BatchLds<T, NB>& L = *reinterpret_cast<BatchLds<T, NB>*>(smem);
   while (true) {
     if (threadIdx.x == 0) {
       const unsigned t = atomicAdd(queue, 1u);
@@ -246,15 +307,39 @@ __global__ __launch_bounds__(kBT) void k_getrf_batched(int batch, const int32_t*
     if (bad || n == 0) {
       if (threadIdx.x == 0) d_info[i] = bad ? -1 : 0;
     } else {
-      factor_one<T>(n, d_A[i], lda, d_ipiv[i], &d_info[i], L);
+      factor_one<T, NB>(n, d_A[i], lda, d_ipiv[i], &d_info[i], L);
     }
     __syncthreads();
   }
 }
 
+// Workgroups of k_getrf_batched<T, NB> resident per CU (registers and LDS),
+// found once by batched_set_lds_limits.
+int g_resident[2][2] = {{1, 1}, {1, 1}};
+
+template <typename T, int NB>
+int batched_resident() {
+  return g_resident[sizeof(T) == 8 ? 0 : 1][NB == 16 ? 0 : 1];
+}
+
+template <typename T, int NB>
+hipError_t launch_nb(hipStream_t s, int batch, const int32_t* d_n, T* const* d_A, const int32_t* d_lda,
+                     int32_t* const* d_ipiv, int32_t* d_info, int max_n, const int32_t* order, unsigned* queue) {
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t lds = sizeof(BatchLds<T, NB>);
+  const int per_cu = batched_resident<T, NB>();
+  const int grid = cus * per_cu < batch ? cus * per_cu : batch;
+  hipLaunchKernelGGL((k_getrf_batched<T, NB>), dim3(grid), dim3(kBT), lds, s, batch, d_n, d_A, d_lda, d_ipiv, d_info,
+                     max_n, order, queue);
+  return hipGetLastError();
+}
+
 template <typename T>
 int launch_batched(void* stream, int batch, const int32_t* d_n, T* const* d_A, const int32_t* d_lda,
-                   int32_t* const* d_ipiv, int32_t* d_info, int max_n, void* d_work, size_t work_bytes) {
+                   int32_t* const* d_ipiv, int32_t* d_info, int max_n, int nb, void* d_work, size_t work_bytes) {
   if (batch < 0) return -2;
   if (batch > 0 && !d_n) return -3;
   if (batch > 0 && !d_A) return -4;
@@ -262,23 +347,20 @@ int launch_batched(void* stream, int batch, const int32_t* d_n, T* const* d_A, c
   if (batch > 0 && !d_ipiv) return -6;
   if (batch > 0 && !d_info) return -7;
   if (max_n < 0 || max_n > kMaxN) return -8;
-  if (!d_work) return -9;
-  if (work_bytes < batched_workspace_bytes(batch)) return -10;
+  if (nb != 0 && nb != 16 && nb != 32) return -9;
+  if (!d_work) return -10;
+  if (work_bytes < batched_workspace_bytes(batch)) return -11;
   if (batch == 0) return 0;
   if (batched_set_lds_limits() != hipSuccess) return MLU_ERR_HIP;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   unsigned* queue = reinterpret_cast<unsigned*>(d_work);
   int32_t* order = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_work) + 256);
   hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, batch, d_n, max_n, order, queue);
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MLU_ERR_HIP;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return MLU_ERR_HIP;
-  const size_t lds = sizeof(BatchLds<T>);
-  const int per_cu = (int)((160u * 1024u) / lds) >= 2 ? 2 : 1;
-  const int grid = cus * per_cu < batch ? cus * per_cu : batch;
-  hipLaunchKernelGGL((k_getrf_batched<T>), dim3(grid), dim3(kBT), lds, s, batch, d_n, d_A, d_lda, d_ipiv, d_info,
-                     max_n, order, queue);
-  return hipGetLastError() == hipSuccess ? 0 : MLU_ERR_HIP;
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  const int use = nb != 0 ? nb : kBatchDefaultNB;
+  const hipError_t e = use == 16 ? launch_nb<T, 16>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue)
+                                 : launch_nb<T, 32>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue);
+  return e == hipSuccess ? 0 : MLU_ERR_HIP;
 }
 
 }  // namespace
@@ -293,11 +375,17 @@ hipError_t batched_set_lds_limits() {
   static bool done = false;
   std::lock_guard<std::mutex> lk(mu);
   if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrf_batched<double>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(BatchLds<double>));
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_getrf_batched<float>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(BatchLds<float>));
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* fn, size_t bytes, int& resident) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    int blocks = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBT, bytes);
+    if (e == hipSuccess) resident = blocks < 1 ? 1 : (blocks > 4 ? 4 : blocks);
+  };
+  set(reinterpret_cast<const void*>(&k_getrf_batched<double, 16>), sizeof(BatchLds<double, 16>), g_resident[0][0]);
+  set(reinterpret_cast<const void*>(&k_getrf_batched<double, 32>), sizeof(BatchLds<double, 32>), g_resident[0][1]);
+  set(reinterpret_cast<const void*>(&k_getrf_batched<float, 16>), sizeof(BatchLds<float, 16>), g_resident[1][0]);
+  set(reinterpret_cast<const void*>(&k_getrf_batched<float, 32>), sizeof(BatchLds<float, 32>), g_resident[1][1]);
   if (e == hipSuccess) done = true;
   return e;
 }
@@ -316,13 +404,13 @@ int mlu_getrf_batched_workspace(int batch, size_t* bytes) {
 }
 
 int mlu_dgetrf_batched(void* stream, int batch, const int32_t* d_n, double* const* d_A, const int32_t* d_lda,
-                       int32_t* const* d_ipiv, int32_t* d_info, int max_n, void* d_work, size_t work_bytes) {
-  return launch_batched<double>(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes);
+                       int32_t* const* d_ipiv, int32_t* d_info, int max_n, int nb, void* d_work, size_t work_bytes) {
+  return launch_batched<double>(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes);
 }
 
 int mlu_sgetrf_batched(void* stream, int batch, const int32_t* d_n, float* const* d_A, const int32_t* d_lda,
-                       int32_t* const* d_ipiv, int32_t* d_info, int max_n, void* d_work, size_t work_bytes) {
-  return launch_batched<float>(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes);
+                       int32_t* const* d_ipiv, int32_t* d_info, int max_n, int nb, void* d_work, size_t work_bytes) {
+  return launch_batched<float>(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes);
 }
 
 }  // extern "C"

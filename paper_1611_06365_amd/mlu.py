@@ -33,8 +33,8 @@ _SIGNATURES = {
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
                        _vp, _vp, _sz], _i),
     "mlu_getrf_batched_workspace": ([_i, ctypes.POINTER(_sz)], _i),
-    "mlu_dgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz], _i),
-    "mlu_sgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp, _sz], _i),
+    "mlu_dgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_sgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _sz], _i),
     "mlu_dtrsm": ([_vp, _c, _c, _i, _i, _vp, _i, _vp, _i], _i),
     "mlu_dgetrs": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i], _i),
     "mlu_dgemm_update": ([_vp, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i], _i),
@@ -113,12 +113,12 @@ def mlu_getrf_batched_workspace(batch) -> tuple[int, int]:
     return rc, out.value
 
 
-def mlu_dgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes) -> int:
-    return _call("mlu_dgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes)
+def mlu_dgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes) -> int:
+    return _call("mlu_dgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes)
 
 
-def mlu_sgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes) -> int:
-    return _call("mlu_sgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, d_work, work_bytes)
+def mlu_sgetrf_batched(stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes) -> int:
+    return _call("mlu_sgetrf_batched", stream, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, nb, d_work, work_bytes)
 
 
 def mlu_dtrsm(stream, uplo, diag, m, nrhs, dT, ldt, dB, ldb) -> int:
@@ -313,7 +313,7 @@ class BatchPlan:
     (with per-matrix pointers into it), info and the workspace.  Built once;
     the matrices it points to are factored in place by `run`."""
 
-    def __init__(self, mats, max_n=None):
+    def __init__(self, mats, max_n=None, nb=0):
         import torch
 
         if not mats:
@@ -330,7 +330,7 @@ class BatchPlan:
             ns.append(int(m.shape[0]))
             ptrs.append(int(m.data_ptr()))
             ldas.append(max(1, int(m.stride(0)) if m.numel() else 1))
-        self.dtype, self.batch = dt, len(mats)
+        self.dtype, self.batch, self.nb = dt, len(mats), int(nb)
         self.max_n = max(ns) if max_n is None else int(max_n)
         offs = [0]
         for n in ns:
@@ -352,16 +352,44 @@ class BatchPlan:
 
         fn = mlu_dgetrf_batched if self.dtype == torch.float64 else mlu_sgetrf_batched
         rc = fn(_stream(stream), self.batch, self.d_n.data_ptr(), self.d_A.data_ptr(), self.d_lda.data_ptr(),
-                self.d_ipiv.data_ptr(), self.info.data_ptr(), self.max_n, self.work.data_ptr(), self.work.numel())
+                self.d_ipiv.data_ptr(), self.info.data_ptr(), self.max_n, self.nb, self.work.data_ptr(), self.work.numel())
         check(rc, "mlu_getrf_batched")
 
     def pivots(self, i):
         return self.ipiv[self.offsets[i]:self.offsets[i + 1]]
 
 
-def getrf_batched(mats, max_n=None, stream=None):
+BATCH_NB_CANDIDATES = (16, 32)
+
+
+def tune_batched(mats, max_n=None, candidates=BATCH_NB_CANDIDATES, reps=2):
+    """Choose the panel width of mlu_?getrf_batched for a batch by timing each
+    candidate on scratch copies of the matrices (the inputs are untouched),
+    on the current stream, the best of `reps` runs each.  Returns
+    (best_nb, {nb: ms})."""
+    import torch
+
+    work = [m.clone() for m in mats]
+    times = {}
+    for nb in candidates:
+        plan = BatchPlan(work, max_n, nb)
+        best = float("inf")
+        for _ in range(reps):
+            for w, m in zip(work, mats):
+                w.copy_(m)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.run()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        times[nb] = best
+    return min(times, key=times.get), times
+
+
+def getrf_batched(mats, max_n=None, stream=None, nb=0):
     """Factor every matrix of the list in place; returns the BatchPlan (its
     `info` and `pivots(i)` are valid once the stream has finished)."""
-    plan = BatchPlan(mats, max_n)
+    plan = BatchPlan(mats, max_n, nb)
     plan.run(stream)
     return plan

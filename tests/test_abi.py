@@ -126,12 +126,12 @@ def test_batched_argument_checks(lib):
     assert lib.mlu_getrf_batched_workspace(-1, ctypes.byref(out)) == -1
     assert lib.mlu_getrf_batched_workspace(10, None) == -2
     assert lib.mlu_getrf_batched_workspace(20000, ctypes.byref(out)) == 0 and out.value >= 20000 * 4
-    base = dict(stream=None, batch=2, d_n=8, d_A=8, d_lda=8, d_ipiv=8, d_info=8, max_n=64, d_work=8,
+    base = dict(stream=None, batch=2, d_n=8, d_A=8, d_lda=8, d_ipiv=8, d_info=8, max_n=64, nb=0, d_work=8,
                 work_bytes=1 << 20)
     for fn in (mlu.mlu_dgetrf_batched, mlu.mlu_sgetrf_batched):
         for key, bad, code in [("batch", -1, -2), ("d_n", None, -3), ("d_A", None, -4), ("d_lda", None, -5),
                                ("d_ipiv", None, -6), ("d_info", None, -7), ("max_n", 513, -8),
-                               ("d_work", None, -9), ("work_bytes", 4, -10)]:
+                               ("nb", 24, -9), ("d_work", None, -10), ("work_bytes", 4, -11)]:
             kw = dict(base)
             kw[key] = bad
             assert fn(*kw.values()) == code, (fn.__name__, key)

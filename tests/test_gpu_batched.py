@@ -46,10 +46,11 @@ def make_batch(seed=0):
     return mats
 
 
-def test_batched_fp64_against_oracle():
+@pytest.mark.parametrize("nb", [16, 32])
+def test_batched_fp64_against_oracle(nb):
     mats = make_batch()
     dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
-    plan = mlu.getrf_batched(dmats)
+    plan = mlu.getrf_batched(dmats, nb=nb)
     info = host(plan.info)
     for i, (a, d) in enumerate(zip(mats, dmats)):
         n = a.shape[0]
@@ -63,7 +64,8 @@ def test_batched_fp64_against_oracle():
         assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-13, (i, n)
 
 
-def test_batched_known_answer_and_zero_pivot():
+@pytest.mark.parametrize("nb", [0, 32])
+def test_batched_known_answer_and_zero_pivot(nb):
     mats, expect = [], []
     for i, n in enumerate([5, 33, 64, 97, 130]):
         A, perm, L, U = G.known_answer(n, n, seed=7 + i)
@@ -73,7 +75,7 @@ def test_batched_known_answer_and_zero_pivot():
         mats.append(G.zero_column(48, seed=4, col=col))
         expect.append(col + 1)
     dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
-    plan = mlu.getrf_batched(dmats)
+    plan = mlu.getrf_batched(dmats, nb=nb)
     info = host(plan.info)
     for i, (a, d) in enumerate(zip(mats, dmats)):
         R = a.copy()
@@ -95,10 +97,11 @@ def test_batched_invalid_entries_are_reported_and_untouched():
     assert torch.equal(big, big0)
 
 
-def test_batched_fp32():
+@pytest.mark.parametrize("nb", [16, 32])
+def test_batched_fp32(nb):
     mats = make_batch(seed=3)[:40]
     dmats = [torch.from_numpy(a.astype(np.float32)).to(DEV) for a in mats]
-    plan = mlu.getrf_batched(dmats)
+    plan = mlu.getrf_batched(dmats, nb=nb)
     info = host(plan.info)
     for i, (a, d) in enumerate(zip(mats, dmats)):
         a32 = a.astype(np.float32).astype(np.float64)
