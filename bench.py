@@ -175,6 +175,63 @@ def batched_section(args, dev):
     return out
 
 
+def et_section(args, A, ipiv, info, work):
+    """Look-ahead LU with early termination of the panel (mlu_dgetrf_et) beside
+    plain look-ahead (mlu_dgetrf, LA) on the bench matrix: the left-looking
+    panel without stopping (force=never), then with the flag, for two planned
+    widths and minimum stop widths.  Each run factors a fresh copy of A
+    (restored outside the timed region), timed with HIP events; the best of two
+    runs.  ET waits on the device once per outer iteration, inside its timed
+    region."""
+    import torch
+
+    from paper_1611_06365_amd import mlu
+
+    M = torch.empty_like(A)
+    widths = {}
+
+    def timed(fn, reps=2):
+        best = None
+        for _ in range(reps + 1):   # the first is a warm-up
+            M.copy_(A)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    rows = []
+    la_ms = {}
+    for nb, min_width, force in ((256, 0, "never"), (256, 0, "signal"), (256, 128, "signal"), (512, 256, "signal")):
+        if nb not in la_ms:
+            la_ms[nb] = timed(lambda: mlu.getrf(M, variant="la", nb=nb, nb_inner=args.nb_inner, ipiv=ipiv,
+                                                info=info, work=work))
+        ok_la = int(info.item())
+
+        def et():
+            widths["w"] = mlu.getrf_et(M, nb=nb, nb_inner=args.nb_inner, force=force, min_width=min_width,
+                                       ipiv=ipiv, info=info, work=work)[2]
+
+        t_et = timed(et)
+        w = widths["w"]
+        row = {"nb": nb, "min_width": min_width, "force": force, "ms_la": round(la_ms[nb], 3),
+               "ms_la_et": round(t_et, 3),
+               "info": [ok_la, int(info.item())],
+               "panels": len(w), "width_min": min(w), "width_max": max(w), "width_mean": round(sum(w) / len(w), 1),
+               "stopped_early": sum(1 for x in w[1:-1] if x < nb)}
+        log(f"ET nb={nb} min_width={min_width} force={force}: {row}")
+        rows.append(row)
+    del M
+    return {"what": "look-ahead with early termination of the left-looking panel (flag raised when RU2 "
+                    "completes; the panel stops after its current 16-column block and the next block size is "
+                    "the width it reached) vs plain look-ahead (RL inner panel)",
+            "n": A.shape[0], "matrix": args.matrix, "rows": rows}
+
+
 def mixed_section(args, dev):
     """FP32-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
     solve (the same entry point with FP64 products and no correction: getrf,
@@ -263,6 +320,7 @@ def main() -> int:
                     help="skip the mixed-precision + refinement measurement")
     ap.add_argument("--mixed-conds", default="1e2,1e5,1e8")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
+    ap.add_argument("--no-et", action="store_true", help="skip the early-termination comparison")
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
@@ -359,6 +417,10 @@ def main() -> int:
             "share_of_step_time": round(gemm_ms / ms, 4),
         }
 
+    et = None
+    if not args.no_et:
+        et = et_section(args, A, ipiv, info, work)
+
     batched = None
     if not args.no_batched:
         batched = batched_section(args, dev)
@@ -401,6 +463,7 @@ def main() -> int:
         "frac_fp64_peak": round(value / (FP64_PEAK_TFLOPS * 1e3), 4),
         "roofline": roof,
         "mixed": mixed,
+        "early_termination": et,
         "batched": batched,
         "cpu_baseline": cpu,
         "check": check,

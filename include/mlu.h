@@ -121,6 +121,38 @@ int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv,
                int iters_limit, void *d_work, size_t work_bytes);
 
 /*
+ * LU with partial pivoting by the look-ahead variant with early termination of
+ * the panel factorization (Section 4.3, "Early termination"; Fig.
+ * "LU_LA_ET").  Each look-ahead panel PF3 is factored by the blocked
+ * left-looking algorithm in nb_inner-wide blocks, which touches nothing to the
+ * right of the current block; when the trailing update RU2 of the same outer
+ * iteration completes, it raises a device flag, the panel stops at the end of
+ * its current block, and the next outer iteration proceeds with the columns
+ * factored so far as its block (the block size adapts).  Result: as
+ * mlu_dgetrf (same factors, pivots, info), computed with the realized panel
+ * widths as the schedule.
+ *  m, n, dA, lda, d_ipiv, d_info, nb, nb_inner: as mlu_dgetrf (nb = the
+ *              planned width of each panel).
+ *  force       0 = the flag is raised by RU2 (the method); 1 = every
+ *              look-ahead panel stops after its first block; 2 = no panel
+ *              stops (plain look-ahead with a left-looking PF3).
+ *  min_width   a look-ahead panel stops only once it has at least this many
+ *              columns (0 = after any block, the method's rule; ignored with
+ *              force = 1).
+ *  h_widths    optional host int32[max_widths]: the realized panel widths, in
+ *              order (they sum to min(m, n)); *n_widths = their number (also
+ *              when it exceeds max_widths, of which only the first are stored).
+ *  d_work      mlu_dgetrf_workspace() bytes.
+ * The host waits on the device once per outer iteration (for the width the
+ * panel reached), so the call returns when the last panel has been factored
+ * and the final updates are enqueued.  FP64 only.
+ * Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
+ */
+int mlu_dgetrf_et(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info, int nb,
+                  int nb_inner, int force, int min_width, int32_t *h_widths, int max_widths, int *n_widths,
+                  void *d_work, size_t work_bytes);
+
+/*
  * Mixed-precision LU with partial pivoting: mlu_dgetrf with the outer trailing
  * updates' products in `precision` (MLU_PREC_FP32, or MLU_PREC_FP64 for
  * exactly mlu_dgetrf).  The factors are those of a matrix within about

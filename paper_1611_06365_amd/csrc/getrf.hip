@@ -32,11 +32,41 @@ __global__ void k_zero(unsigned* p, size_t nwords) {
   if (i < nwords) p[i] = 0u;
 }
 
-// one library-owned stream and two events per device for the look-ahead fork
+// RU2 of outer iteration k is complete (stream order): publish k + 1 to the
+// panel's stream with an agent-scope release.
+__global__ void k_et_signal(unsigned* ru_done, unsigned k1) {
+  if (threadIdx.x == 0) __hip_atomic_store(ru_done, k1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// End of one inner iteration of the look-ahead panel (Section 4.3, early
+// termination): unless the panel has already stopped, it now covers `cols`
+// columns; it stops once RU2 of the current outer iteration has signalled.
+// The flag is read once per inner iteration, so every later launch of the
+// panel sees one stable value.  A panel narrower than min_cols does not stop
+// (0: any width, the rule of the method).
+__global__ void k_et_check(const unsigned* ru_done, unsigned k1, int32_t* stop, int32_t* width, int cols,
+                           int min_cols) {
+  if (threadIdx.x == 0 && *stop == 0) {
+    *width = cols;
+    if (cols >= min_cols && __hip_atomic_load(ru_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= k1)
+      *stop = 1;
+  }
+}
+
+__global__ void k_et_reset(int32_t* stop, int32_t* width) {
+  if (threadIdx.x == 0) {
+    *stop = 0;
+    *width = 0;
+  }
+}
+
+// one library-owned stream and two events per device for the look-ahead fork;
+// early termination adds one event and a pinned word for the panel width
 struct AuxStreams {
   bool ready = false;
   hipStream_t s1 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr, width_ev = nullptr;
+  int32_t* h_width = nullptr;
 };
 
 // Look-ahead overlap: RU2 leaves the CUs with id < kLaReserve (mod 8) in every
@@ -63,6 +93,10 @@ hipError_t get_aux(AuxStreams** out) {
     if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.ru1, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.width_ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&a.h_width), sizeof(int32_t), hipHostMallocDefault)) !=
+        hipSuccess)
+      return e;
     a.ready = true;
   }
   *out = &a;
@@ -209,6 +243,101 @@ hipError_t run_ll(hipStream_t s, const Ctx& c, const std::vector<int>& sched, in
   return hipSuccess;
 }
 
+// PF3 / the initial panel of the early-termination variant: the panel rows
+// j..m-1, columns j..j+b-1, factored by the blocked left-looking algorithm
+// with b_i-wide blocks (Section 4.3): before block [jj, jj+bw) it receives the
+// panel's earlier interchanges (lazy), LL1 solves its rows j..jj-1 with the
+// panel's unit lower triangle, LL2 updates its rows jj.. with the panel's
+// columns to its left, LL3 factors it (interchanges applied to the panel's
+// columns to its left only).  Nothing right of the block is touched, so the
+// panel can stop after any block.  With `et`, every block after the first
+// takes the stop flag and a check follows each block.
+hipError_t factor_panel_ll(hipStream_t s, const Ctx& c, int j, int b, EtWork* et, unsigned k1, int min_cols) {
+  for (int jj = j; jj < j + b; jj += c.bi) {
+    const int bw = (j + b - jj) < c.bi ? (j + b - jj) : c.bi;
+    const int32_t* skip = (et != nullptr && jj > j) ? &et->stop : nullptr;
+    if (jj > j) {
+      MLU_TRY(laswp(s, c.A, c.lda, c.m, j, jj, c.ipiv, jj, jj + bw, 0, 0, c.info, skip));
+      MLU_TRY(trsm_left(s, true, true, jj - j, bw, c.at(j, j), c.lda, c.at(j, jj), c.lda, skip));     // LL1
+      if (jj < c.m)
+        MLU_TRY(gemm_update(s, c.m - jj, bw, jj - j, c.at(jj, j), c.lda, c.at(j, jj), c.lda, c.at(jj, jj),
+                            c.lda, false, kPrecF64, false, skip));                                        // LL2
+    }
+    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, jj - j, 0,
+                         skip));                                                                          // LL3
+    if (et != nullptr) {
+      hipLaunchKernelGGL(k_et_check, dim3(1), dim3(64), 0, s, &et->ru_done, k1, &et->stop, &et->width,
+                         jj + bw - j, min_cols);
+      MLU_TRY(hipGetLastError());
+    }
+  }
+  return hipSuccess;
+}
+
+// Look-ahead with early termination of the panel factorization (Section 4.3,
+// Fig. "LU_LA_ET"): as run_la, with PF3 the left-looking inner LU above and
+// a signal after RU2.  The host waits once per outer iteration for the width
+// the panel reached (the next iteration's b); `force` = 1 stops every
+// look-ahead panel after its first block, 2 never stops it.
+hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force, int min_cols,
+                     std::vector<int>* widths) {
+  AuxStreams* aux = nullptr;
+  MLU_TRY(get_aux(&aux));
+  hipStream_t s1 = aux->s1;
+  const int mn = c.m < c.n ? c.m : c.n;
+  int b = nb < mn ? nb : mn;
+  MLU_TRY(factor_panel_ll(s0, c, 0, b, nullptr, 0, 0));                          // initial A_BR^P
+  widths->push_back(b);
+  int j = 0;
+  for (unsigned k = 0; j < mn; ++k) {
+    MLU_TRY(laswp(s0, c.A, c.lda, c.m, j, j + b, c.ipiv, 0, j, j + b, c.n, c.info));
+    const int jn = j + b;
+    const int bp = (mn - jn) < nb ? (mn - jn) : nb;
+    int bnext = 0;
+    if (bp > 0) {
+      const unsigned k1 = k + 1;
+      MLU_TRY(hipEventRecord(aux->fork, s0));
+      const int c0 = jn + bp;
+      unsigned* q = c.queue->ctr[k % kQueueSlots];
+      unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
+      if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
+      MLU_TRY(hipEventRecord(aux->ru1, s0));
+      const int mr = c.m - jn, nr = c.n - c0;
+      MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
+                         kLaReserve, 0, true, c.prec));
+      if (force != 2) {   // RU2 done: tell the panel
+        hipLaunchKernelGGL(k_et_signal, dim3(1), dim3(64), 0, s0, &et->ru_done, k1);
+        MLU_TRY(hipGetLastError());
+      }
+      MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
+      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));          // PF1, PF2
+      hipLaunchKernelGGL(k_et_reset, dim3(1), dim3(64), 0, s1, &et->stop, &et->width);
+      MLU_TRY(hipGetLastError());
+      if (force == 1) {   // as if RU2 had finished before the panel started
+        hipLaunchKernelGGL(k_et_signal, dim3(1), dim3(64), 0, s1, &et->ru_done, k1);
+        MLU_TRY(hipGetLastError());
+      }
+      MLU_TRY(factor_panel_ll(s1, c, jn, bp, et, k1, force == 1 ? 0 : min_cols));  // PF3, may stop early
+      MLU_TRY(hipMemcpyAsync(aux->h_width, &et->width, sizeof(int32_t), hipMemcpyDeviceToHost, s1));
+      MLU_TRY(hipEventRecord(aux->width_ev, s1));
+      MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
+      MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
+                         0, kLaHelpers, false, c.prec));
+      MLU_TRY(hipEventRecord(aux->join, s1));
+      MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
+      MLU_TRY(hipEventSynchronize(aux->width_ev));
+      bnext = *aux->h_width;
+      if (bnext < 1 || bnext > bp) return hipErrorUnknown;
+      widths->push_back(bnext);
+    } else {
+      MLU_TRY(update_cols(s0, c, j, b, jn, c.n));                                // RU1, RU2
+    }
+    j = jn;
+    b = bnext;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes) {
@@ -313,6 +442,41 @@ int mlu_dsgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
                 void* d_work, size_t work_bytes) {
   return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision, h_schedule,
                      n_schedule, iters_limit, d_work, work_bytes, 1);
+}
+
+int mlu_dgetrf_et(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int nb,
+                  int nb_inner, int force, int min_width, int32_t* h_widths, int max_widths, int* n_widths,
+                  void* d_work, size_t work_bytes) {
+  const int mn = m < n ? m : n;
+  if (m < 0 || m > kPanelMaxRows) return -2;
+  if (n < 0) return -3;
+  if (mn > 0 && !dA) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (mn > 0 && !d_ipiv) return -6;
+  if (!d_info) return -7;
+  if (nb < 1) return -8;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -9;
+  if (force < 0 || force > 2) return -10;
+  if (min_width < 0) return -11;
+  if (max_widths > 0 && !h_widths) return -12;
+  if (max_widths < 0) return -13;
+  if (!n_widths) return -14;
+  if (!d_work) return -15;
+  if (work_bytes < workspace_bytes()) return -16;
+  *n_widths = 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
+  if (mn == 0) return 0;
+  if (zero_bytes(s, d_work, sizeof(Workspace)) != hipSuccess) return MLU_ERR_HIP;
+  unsigned epoch = 0;
+  Workspace* ws = reinterpret_cast<Workspace*>(d_work);
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, kPrecF64, &epoch};
+  c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
+  std::vector<int> widths;
+  if (run_la_et(s, c, nb, &ws->et, force, min_width, &widths) != hipSuccess) return MLU_ERR_HIP;
+  *n_widths = (int)widths.size();
+  for (int i = 0; i < (int)widths.size() && i < max_widths; ++i) h_widths[i] = widths[i];
+  return 0;
 }
 
 int mlu_dtrsm(void* stream, char uplo, char diag, int m, int nrhs, const double* dT, int ldt, double* dB,

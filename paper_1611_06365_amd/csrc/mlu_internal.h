@@ -53,9 +53,19 @@ struct QueueWork {
   alignas(128) unsigned ctr[kQueueSlots][kXcd * kQueueStride];
 };
 
+// Early termination of the look-ahead panel: RU2 of outer iteration k stores
+// k + 1 into ru_done; after each inner block of the panel a check raises stop
+// once that is seen, and width records the panel columns factored so far.
+struct EtWork {
+  alignas(128) unsigned ru_done;
+  int32_t stop;
+  int32_t width;
+};
+
 struct Workspace {
   PanelWork panel;
   QueueWork queue;
+  EtWork et;
 };
 
 size_t workspace_bytes();
@@ -102,9 +112,11 @@ hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 // (cl columns of it to the block's left, cr to its right, same rows), the
 // block's interchanges are also applied to those columns and the block's top
 // bw rows of the right columns are solved with its unit lower triangle.
+// A nonzero *skip (a device flag written before the launch in stream order)
+// makes every workgroup return at once.
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0,
                         int32_t* ipiv, int32_t* info, PanelWork* work, unsigned epoch, int cl = 0,
-                        int cr = 0);
+                        int cr = 0, const int32_t* skip = nullptr);
 
 // Apply interchanges ipiv[k1 .. k2) (1-based values, each >= its own index and
 // < m) to columns [ca0, ca1) and [cb0, cb1) of the m-row matrix A.

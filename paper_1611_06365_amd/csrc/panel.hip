@@ -704,8 +704,11 @@ template <int BW, int MAXW>
 __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
                                               int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
                                               PanelWork* __restrict__ work, int nwg, unsigned epoch, int cl,
-                                              int cr) {
+                                              int cr, const int32_t* __restrict__ skip) {
   static_assert(BW % U == 0, "BW must be a multiple of U");
+  // the flag was written by an earlier launch on the stream, so every
+  // workgroup reads the same value and they all leave or all stay
+  if (skip != nullptr && *skip != 0) return;
   __shared__ __attribute__((aligned(16))) double s_cand[2][NWAVE][BW];
   __shared__ __attribute__((aligned(16))) double s_drow[2][BW];
   __shared__ __attribute__((aligned(16))) double s_prow[2][BW];
@@ -771,27 +774,27 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
 
 template <int BW>
 hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip) {
   const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
   if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
   if (nwg <= 16)
     hipLaunchKernelGGL((k_panel<BW, 16>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, nwg,
-                       epoch, cl, cr);
+                       epoch, cl, cr, skip);
   else
     hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
-                       work, nwg, epoch, cl, cr);
+                       work, nwg, epoch, cl, cr, skip);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip) {
   if (m <= 0 || bw <= 0) return hipSuccess;
   if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows || cl < 0 || cr < 0) return hipErrorInvalidValue;
   ipiv += row0;
-  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr);
-  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr);
+  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, skip);
+  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, skip);
 }
 
 size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }

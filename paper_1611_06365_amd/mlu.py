@@ -29,6 +29,7 @@ _SIGNATURES = {
     "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
     "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dgetrf_et": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz], _i),
     "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
                        _vp, _vp, _sz], _i),
@@ -224,6 +225,38 @@ def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ip
                          work.numel())
         check(rc, "mlu_dsgetrf")
     return ipiv, info
+
+
+ET_FORCE_IDS = {"signal": 0, "always": 1, "never": 2}
+
+
+def mlu_dgetrf_et(stream, m, n, dA, lda, d_ipiv, d_info, nb, nb_inner, force, min_width, h_widths, max_widths,
+                  n_widths, d_work, work_bytes) -> int:
+    return _call("mlu_dgetrf_et", stream, m, n, dA, lda, d_ipiv, d_info, nb, nb_inner, force, min_width, h_widths,
+                 max_widths, n_widths, d_work, work_bytes)
+
+
+def getrf_et(A, nb=256, nb_inner=0, force="signal", min_width=0, ipiv=None, info=None, work=None, stream=None):
+    """Factor A in place by look-ahead LU with early termination of the panel
+    (mlu_dgetrf_et); returns (ipiv, info, widths) with widths the realized
+    panel widths (a host list).  The call waits on the device once per outer
+    iteration."""
+    import torch
+
+    pa, lda = _rowmajor(A, "A")
+    m, n = A.shape
+    k = min(m, n)
+    ipiv = torch.empty(max(k, 1), dtype=torch.int32, device=A.device) if ipiv is None else ipiv
+    info = torch.empty(1, dtype=torch.int32, device=A.device) if info is None else info
+    work = workspace(A.device) if work is None else work
+    cap = max(k, 1)
+    arr = (ctypes.c_int32 * cap)()
+    cnt = ctypes.c_int(0)
+    rc = mlu_dgetrf_et(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), nb, nb_inner,
+                       ET_FORCE_IDS[force], min_width, ctypes.cast(arr, ctypes.c_void_p), cap,
+                       ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p), work.data_ptr(), work.numel())
+    check(rc, "mlu_dgetrf_et")
+    return ipiv, info, [int(arr[i]) for i in range(min(cnt.value, cap))]
 
 
 def gesv_ir(A, B, precision="fp32", tol=1e-13, max_iter=10, variant="la", nb=256, nb_inner=0, X=None, work=None,

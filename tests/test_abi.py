@@ -138,3 +138,20 @@ def test_batched_argument_checks(lib):
         kw = dict(base)
         kw["batch"] = 0
         assert fn(*kw.values()) == 0
+
+
+def test_et_argument_checks(lib):
+    import ctypes
+
+    from paper_1611_06365_amd import mlu
+
+    cnt = ctypes.c_int(-5)
+    base = dict(stream=None, m=4, n=4, dA=8, lda=4, d_ipiv=8, d_info=8, nb=2, nb_inner=0, force=0, min_width=0,
+                h_widths=None, max_widths=0, n_widths=ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p), d_work=8, work_bytes=1 << 40)
+    for key, bad, code in [("m", -1, -2), ("n", -1, -3), ("dA", None, -4), ("lda", 3, -5), ("d_ipiv", None, -6),
+                           ("d_info", None, -7), ("nb", 0, -8), ("nb_inner", 17, -9), ("force", 3, -10),
+                           ("min_width", -1, -11), ("max_widths", 4, -12), ("max_widths", -1, -13),
+                           ("n_widths", None, -14), ("d_work", None, -15), ("work_bytes", 16, -16)]:
+        kw = dict(base)
+        kw[key] = bad
+        assert mlu.mlu_dgetrf_et(*kw.values()) == code, key
