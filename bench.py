@@ -232,6 +232,37 @@ def et_section(args, A, ipiv, info, work):
             "n": A.shape[0], "matrix": args.matrix, "rows": rows}
 
 
+def selector_section(args):
+    """The learned selector: its choice for the bench workload, its inference
+    latency through the C ABI (mlu_select) and in Python, and the regret on
+    the held-out orders from the committed training report."""
+    from paper_1611_06365_amd import mlu
+    from paper_1611_06365_amd import selector as S
+
+    if not os.path.exists(S.MODEL_PATH):
+        return None
+    choice = mlu.select(args.n, "fp64")
+    reps = 2000
+    t0 = time.perf_counter()
+    for i in range(reps):
+        mlu.select(64 + i, "fp64")
+    c_us = (time.perf_counter() - t0) / reps * 1e6
+    sel = S.Selector()
+    t0 = time.perf_counter()
+    for i in range(reps):
+        sel.predict(64 + i, "fp64")
+    py_us = (time.perf_counter() - t0) / reps * 1e6
+    report = None
+    rp = os.path.join(os.path.dirname(S.MODEL_PATH), "selector_report.json")
+    if os.path.exists(rp):
+        with open(rp) as f:
+            report = json.load(f)
+    out = {"choice_for_workload": {"variant": choice[0], "nb": choice[1]},
+           "inference_us_c_abi": round(c_us, 2), "inference_us_python": round(py_us, 2), "training_report": report}
+    log(f"selector: {out}")
+    return out
+
+
 def mixed_section(args, dev):
     """FP32-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
     solve (the same entry point with FP64 products and no correction: getrf,
@@ -417,6 +448,8 @@ def main() -> int:
             "share_of_step_time": round(gemm_ms / ms, 4),
         }
 
+    sel = selector_section(args)
+
     et = None
     if not args.no_et:
         et = et_section(args, A, ipiv, info, work)
@@ -464,6 +497,7 @@ def main() -> int:
         "roofline": roof,
         "mixed": mixed,
         "early_termination": et,
+        "selector": sel,
         "batched": batched,
         "cpu_baseline": cpu,
         "check": check,

@@ -224,6 +224,23 @@ int mlu_sgetrf_batched(void *stream, int batch, const int32_t *d_n, float *const
                        size_t work_bytes);
 
 /*
+ * The learned selector (the block-size study of Section 5 as a model): given
+ * the order n and the product precision, choose the variant and the outer
+ * block size b for mlu_dgetrf / mlu_dsgetrf.  Host function, no device work.
+ *  model       host float array written by the selector's pack(): header
+ *              [3, hidden, n_out, 3], n_out (variant, b) pairs, then three
+ *              dense layers (row-major W, then b) of a 3 -> hidden -> hidden
+ *              -> n_out perceptron with ReLU; outputs are predicted log
+ *              times, the smallest wins (first on ties).
+ *  model_len   its length in floats.
+ *  n           matrix order (>= 1); precision MLU_PREC_FP64 or _FP32.
+ *  variant, nb receive the choice.
+ * Returns 0 or -i for an invalid argument i (a malformed model is argument 1
+ * or 2).
+ */
+int mlu_select(const float *model, int model_len, int n, int precision, int *variant, int *nb);
+
+/*
  * Triangular solve with several right-hand sides, left side, no transpose:
  * B := T^{-1} B (RL2 / PF1 / RU1 / LL1 use uplo 'L', diag 'U' on trilu(A11),
  * Fig. "LU").

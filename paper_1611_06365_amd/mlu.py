@@ -29,6 +29,7 @@ _SIGNATURES = {
     "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
     "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_select": ([_vp, _i, _i, _i, _vp, _vp], _i),
     "mlu_dgetrf_et": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz], _i),
     "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
@@ -225,6 +226,38 @@ def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ip
                          work.numel())
         check(rc, "mlu_dsgetrf")
     return ipiv, info
+
+
+VARIANT_NAMES = {0: "rl", 1: "ll", 2: "la"}
+
+
+def select(n, precision="fp64", model=None):
+    """The learned selector through the C ABI (mlu_select): (variant, nb) for
+    an n x n factorization.  `model`: a packed float list (selector.pack);
+    default, the package's trained model."""
+    if model is None:
+        from . import selector
+
+        model = _packed_default(selector)
+    arr = (ctypes.c_float * len(model))(*model)
+    v, nb = ctypes.c_int(-1), ctypes.c_int(-1)
+    rc = _call("mlu_select", ctypes.cast(arr, ctypes.c_void_p), len(model), int(n), PRECISION_IDS[precision],
+               ctypes.cast(ctypes.byref(v), ctypes.c_void_p), ctypes.cast(ctypes.byref(nb), ctypes.c_void_p))
+    check(rc, "mlu_select")
+    return VARIANT_NAMES[v.value], nb.value
+
+
+_PACKED = None
+
+
+def _packed_default(selector):
+    global _PACKED
+    if _PACKED is None:
+        import json
+
+        with open(selector.MODEL_PATH) as f:
+            _PACKED = selector.pack(json.load(f))
+    return _PACKED
 
 
 ET_FORCE_IDS = {"signal": 0, "always": 1, "never": 2}
