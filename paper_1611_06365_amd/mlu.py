@@ -231,17 +231,19 @@ def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ip
 VARIANT_NAMES = {0: "rl", 1: "ll", 2: "la"}
 
 
+def packed_model(model):
+    """A packed float list (selector.pack) as the ctypes array mlu_select reads."""
+    return (ctypes.c_float * len(model))(*model)
+
+
 def select(n, precision="fp64", model=None):
     """The learned selector through the C ABI (mlu_select): (variant, nb) for
-    an n x n factorization.  `model`: a packed float list (selector.pack);
-    default, the package's trained model."""
-    if model is None:
-        from . import selector
-
-        model = _packed_default(selector)
-    arr = (ctypes.c_float * len(model))(*model)
+    an n x n factorization.  `model`: a packed float list (selector.pack) or a
+    packed_model() array; default, the package's trained model."""
+    arr = _packed_default() if model is None else (model if isinstance(model, ctypes.Array) else
+                                                    packed_model(model))
     v, nb = ctypes.c_int(-1), ctypes.c_int(-1)
-    rc = _call("mlu_select", ctypes.cast(arr, ctypes.c_void_p), len(model), int(n), PRECISION_IDS[precision],
+    rc = _call("mlu_select", ctypes.cast(arr, ctypes.c_void_p), len(arr), int(n), PRECISION_IDS[precision],
                ctypes.cast(ctypes.byref(v), ctypes.c_void_p), ctypes.cast(ctypes.byref(nb), ctypes.c_void_p))
     check(rc, "mlu_select")
     return VARIANT_NAMES[v.value], nb.value
@@ -250,13 +252,15 @@ def select(n, precision="fp64", model=None):
 _PACKED = None
 
 
-def _packed_default(selector):
+def _packed_default():
     global _PACKED
     if _PACKED is None:
         import json
 
+        from . import selector
+
         with open(selector.MODEL_PATH) as f:
-            _PACKED = selector.pack(json.load(f))
+            _PACKED = packed_model(selector.pack(json.load(f)))
     return _PACKED
 
 
