@@ -318,6 +318,120 @@ __device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int 
       }
 }
 
+// A 64 x 64 tile of C := C - A B in FP64, for launches with too few 128 x 128
+// tiles to fill the chip (the small trailing matrices at the end of a
+// factorization, the panel's inner updates): four waves in a 2 x 2 grid, each
+// owning 32 x 32 of C as 2 x 2 MFMA blocks; the K stages, the LDS double
+// buffer, the negated B and the C-preloaded accumulators are as in gemm_tile.
+constexpr int SBM = 64, SBN = 64;
+constexpr int LDS_SB = SBN + 4;
+
+template <bool VEC>
+__device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                                int lda, const double* __restrict__ B, int ldb,
+                                                double* __restrict__ C, int ldc) {
+  __shared__ double As[2][SBM * LDS_A];
+  __shared__ double Bs[2][BK * LDS_SB];
+
+  const int row0 = tm * SBM, col0 = tn * SBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lq = lane >> 4;
+  // global -> register staging: A row ar, 4 k's from ac; B row br, 4 j's from bc
+  const int ar = tid >> 2, ac = (tid & 3) * 4;
+  const int br = tid >> 4, bc = (tid & 15) * 4;
+  const bool interior_mn = (row0 + SBM <= m) && (col0 + SBN <= n);
+
+  double ra[4], rb[4];
+  auto gload = [&](int k0) {
+    const bool full = VEC && interior_mn && (k0 + BK <= k);
+    if (full) {
+      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double2 x = pa[e];
+        ra[2 * e] = x.x;
+        ra[2 * e + 1] = x.y;
+        const double2 y = pb[e];
+        rb[2 * e] = -y.x;
+        rb[2 * e + 1] = -y.y;
+      }
+    } else {
+      const int gr = row0 + ar;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gk = k0 + ac + e;
+        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
+      const int gk = k0 + br;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gc = col0 + bc + e;
+        rb[e] = (gk < k && gc < n) ? -B[(size_t)gk * ldb + gc] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    double* pa = &As[buf][ar * LDS_A + ac];
+    double* pb = &Bs[buf][br * LDS_SB + bc];
+#pragma unroll
+    for (int e = 0; e < 4; e += 2) {
+      *reinterpret_cast<double2*>(pa + e) = make_double2(ra[e], ra[e + 1]);
+      *reinterpret_cast<double2*>(pb + e) = make_double2(rb[e], rb[e + 1]);
+    }
+  };
+
+  // lane (li, lq) of a 16 x 16 f64 block holds rows lq + 4 r of column li
+  v4d acc[2][2];
+  double* const cbase = C + (size_t)(row0 + wm * 32 + lq) * ldc + col0 + wn * 32 + li;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + i * 16 + lq + 4 * r;
+        const int col = col0 + wn * 32 + j * 16 + li;
+        acc[i][j][r] = (interior_mn || (row < m && col < n)) ? cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] : 0.0;
+      }
+
+  const int nk = (k + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      double a[2], b[2];
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        a[blk] = As[buf][(wm * 32 + blk * 16 + li) * LDS_A + 4 * lq + st];
+        b[blk] = Bs[buf][(4 * lq + st) * LDS_SB + wn * 32 + blk * 16 + li];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + i * 16 + lq + 4 * r;
+        const int col = col0 + wn * 32 + j * 16 + li;
+        if (interior_mn || (row < m && col < n)) cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] = acc[i][j][r];
+      }
+}
+
 // one tile in the requested product precision
 template <bool VEC, int PREC>
 __device__ __forceinline__ void tile_any(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
@@ -348,6 +462,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, c
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
   tile_any<VEC, PREC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
+// The 64 x 64 tile form of both (FP64 only), chosen by the host for launches
+// with fewer than kSmallTiles 128 x 128 tiles.
+constexpr int kSmallTiles = 128;   // half the CUs of the device
+template <bool VEC>
+__global__ __launch_bounds__(256, 2) void k_gemm_small(int m, int n, int k, const double* __restrict__ A, int lda,
+                                                       const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                                       int ldc, int tiles_m, int tiles_n,
+                                                       const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;   // a flag the caller raised on the device
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
+  gemm_tile_small<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
 // Persistent form for the look-ahead variant's RU2: queue x holds the logical
@@ -431,6 +559,14 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
   if (e0) {
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
+  }
+  if (prec == kPrecF64 && tiles < kSmallTiles) {   // few big tiles: four times as many small ones
+    const int sm = (m + SBM - 1) / SBM, sn = (n + SBN - 1) / SBN;
+    if (vec) hipLaunchKernelGGL(k_gemm_small<true>, dim3((unsigned)(sm * sn)), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, sm, sn, skip);
+    else hipLaunchKernelGGL(k_gemm_small<false>, dim3((unsigned)(sm * sn)), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, sm, sn, skip);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+    return e;
   }
   const dim3 grid((unsigned)tiles), block(256);
   if (trailing) {
