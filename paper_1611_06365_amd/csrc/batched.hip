@@ -7,18 +7,19 @@
 // first, so that the launch's tail holds small ones); a persistent grid of
 // 512-thread workgroups takes matrices from an atomic queue in that order.
 // One workgroup factors one matrix at a time, NB (16 or 32) columns per step:
-//   1. the (n - j) x NB panel is loaded into LDS and factored there with
-//      partial pivoting (argmax by wave reduction, first row on ties; the
-//      swap, the scaling and the rank-1 update in LDS);
-//   2. each thread owns columns outside the panel and applies the panel's
-//      interchanges to them in order (no barrier needed);
-//   3. A12 is staged into LDS 64 columns at a time and multiplied by the
-//      inverse of the panel's unit lower triangle (computed once per panel),
-//      U12 := trilu(A11)^-1 A12, written back, and the trailing matrix is
-//      updated with the chunk, A22 -= A21 U12, 4 x 4 register tiles of FMAs
-//      with A21 read from the LDS panel.  (FP64 vector and matrix peaks are
-//      equal on this part; the operands are small and irregular, so the
-//      update stays on the VALU.)
+//   1. the (n - j) x NB panel is held in registers, one row per thread, and
+//      factored with partial pivoting.  Rows are not moved: each thread
+//      tracks the position its row has reached under the interchanges.  Per
+//      column, a DPP wave argmax (first position on ties), each wave's best
+//      row copied into LDS, one barrier, then every thread picks the winner,
+//      reads its row from LDS and updates its own row in registers;
+//   2. the panel's interchanges are applied to the columns outside it,
+//      gathered: each thread owns a column and loads every moved row before
+//      storing any (no chain of dependent swaps);
+//   3. per 64 columns of A12: U12 := trilu(A11)^-1 A12 by forward
+//      substitution, eight threads per column; then A22 -= A21 U12 on the
+//      matrix cores (v_mfma 16 x 16 x 4 in the operand precision), 16 x 16
+//      blocks spread over the waves, A21 read from an LDS copy of the panel.
 // Matrices are row-major (element (i, j) at A[i*lda + j]), in place.
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
@@ -39,10 +40,10 @@ struct BatchLds {
   static constexpr int kP = NB + 1;   // LDS pitch of the panel
   T P[kMaxN * kP];         // the factored panel (L11\U11 over L21), rows 0 .. n-j-1
   T U[NB * kUC];           // U12 chunk
-  T prow[NB];              // the pivot row of the current column
-  T wv[kBT / kWave];
-  int wr[kBT / kWave];
-  int src[kMaxN];          // after the panel: the row now at position r came from src[r]
+  T cand[2][kBT / kWave][NB];   // each wave's candidate pivot row, by column parity
+  T wv[2][kBT / kWave];
+  int wr[2][kBT / kWave];
+  int16_t src[kMaxN];      // after the panel: the row now at position r came from src[r]
   int piv[NB];
   int item;
 };
@@ -69,17 +70,62 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row_of(int lq, int r) { return 4 * lq + r; }
 };
 
+// Cross-lane moves by DPP (no LDS traffic): quad_perm [1,0,3,2] (lane ^ 1),
+// [2,3,0,1] (lane ^ 2), row_half_mirror and row_mirror combine the 16 lanes of
+// a row; readlane combines the four rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ double lane_val(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ float lane_val(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int lane_val(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T w) {
+  auto mx = [](T a, T b) { return a > b ? a : b; };
+  w = mx(w, dpp_mov<0xB1>(w));
+  w = mx(w, dpp_mov<0x4E>(w));
+  w = mx(w, dpp_mov<0x141>(w));
+  w = mx(w, dpp_mov<0x140>(w));
+  return mx(mx(lane_val(w, 0), lane_val(w, 16)), mx(lane_val(w, 32), lane_val(w, 48)));
+}
+
+// (largest value, smallest position among the lanes holding it) over the
+// wave; the result is the same in every lane.  Values are never NaN here
+// (non-candidates carry -1 and position INT_MAX).
 template <typename T>
 __device__ __forceinline__ void wave_argmax_t(T& v, int& r) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const T ov = __shfl_xor(v, off);
-    const int orr = __shfl_xor(r, off);
-    if (ov > v || (ov == v && orr < r)) {
-      v = ov;
-      r = orr;
-    }
+  const T w = wave_max(v);
+  const unsigned long long tie = __ballot(v == w);
+  int rr;
+  if (__popcll(tie) == 1) {
+    rr = __builtin_amdgcn_readlane(r, __ffsll((long long)tie) - 1);
+  } else {
+    int x = (v == w) ? r : INT_MAX;
+    x = min(x, dpp_mov<0xB1>(x));
+    x = min(x, dpp_mov<0x4E>(x));
+    x = min(x, dpp_mov<0x141>(x));
+    x = min(x, dpp_mov<0x140>(x));
+    rr = min(min(lane_val(x, 0), lane_val(x, 16)), min(lane_val(x, 32), lane_val(x, 48)));
   }
+  v = w;
+  r = rr;
 }
 
 template <typename T, int NB>
@@ -109,6 +155,11 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       if (c < nb) {   // uniform: only the last panel is narrower
+        // one barrier per column: each wave's best lane copies its row into
+        // LDS (buffers alternate with the column's parity, so the next
+        // column's writes cannot meet this column's reads), and every thread
+        // reads the winner's row from there
+        const int par = c & 1;
         T bv = T(-1);
         int bp = INT_MAX;
         const T av = fabs(v[c]);
@@ -116,43 +167,54 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
           bv = av;
           bp = pos;
         }
+        const int mine = bp;
         wave_argmax_t(bv, bp);
+        if (bp != INT_MAX && mine == bp) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) L.cand[par][wave][cc] = v[cc];
+        }
         if (lane == 0) {
-          L.wv[wave] = bv;
-          L.wr[wave] = bp;
+          L.wv[par][wave] = bv;
+          L.wr[par][wave] = bp;
         }
         __syncthreads();
-        T pm = L.wv[0];
-        int p = L.wr[0];
+        T pm = L.wv[par][0];
+        int p = L.wr[par][0], ws = 0;
 #pragma unroll
         for (int w = 1; w < kBT / kWave; ++w)
-          if (L.wv[w] > pm || (L.wv[w] == pm && L.wr[w] < p)) {
-            pm = L.wv[w];
-            p = L.wr[w];
+          if (L.wv[par][w] > pm || (L.wv[par][w] == pm && L.wr[par][w] < p)) {
+            pm = L.wv[par][w];
+            p = L.wr[par][w];
+            ws = w;
           }
         p = __builtin_amdgcn_readfirstlane(p);
-        if (p >= rows) p = c;   // no comparable entry (a column of NaNs): keep the row
+        ws = __builtin_amdgcn_readfirstlane(ws);
+        if (p >= rows) {   // no comparable entry (a column of NaNs): keep the row at position c
+          p = c;
+          ws = 0;
+          if (live && pos == c) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) L.cand[par][0][cc] = v[cc];
+          }
+          __syncthreads();
+        }
+        const T* prow = L.cand[par][ws];
         if (tid == 0) L.piv[c] = p;
         const bool me = live && pos == p;
-        if (me) {
-#pragma unroll
-          for (int cc = 0; cc < NB; ++cc) L.prow[cc] = v[cc];
-        }
-        __syncthreads();
         if (me) {   // the interchange of positions c and p
           live = false;
           pos = c;
         } else if (live && pos == c) {
           pos = p;
         }
-        const T pv = L.prow[c];
+        const T pv = prow[c];
         if (pv == T(0)) {
           if (j + c < zero_col) zero_col = j + c;   // same value in every thread
         } else if (live) {
           const T l = v[c] / pv;
           v[c] = l;
 #pragma unroll
-          for (int cc = c + 1; cc < NB; ++cc) v[cc] -= l * L.prow[cc];
+          for (int cc = c + 1; cc < NB; ++cc) v[cc] -= l * prow[cc];
         }
       }
     }
@@ -166,7 +228,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         if (cc < nb) a[cc] = v[cc];
         L.P[pos * kP + cc] = v[cc];
       }
-      L.src[pos] = r;
+      L.src[pos] = (int16_t)r;
     }
     __syncthreads();
     if (tid < nb) ipiv[j + tid] = j + L.piv[tid] + 1;
@@ -227,26 +289,42 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         const int li = lane & 15, lq = lane >> 4;
         const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16, npair = nrb * nsb;
         T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
-        for (int pp = wave; pp < npair; pp += kBT / kWave) {
-          const int rb = pp / nsb, cb = (pp - rb * nsb) * 16 + li;
-          const bool cok = cb < cw;
-          acc_t acc;
+        // each wave walks its 16 x 16 blocks with the next block's C loads
+        // issued before the current block's MFMAs (one block of prefetch)
+        constexpr int kWaves = kBT / kWave;
+        auto load_c = [&](int pp, acc_t& acc, int& rb, int& cb) {
+          rb = pp / nsb;
+          cb = (pp - rb * nsb) * 16 + li;
+          const int col = min(cb, cw - 1);   // a clamped lane is computed and not stored
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
-            acc[r] = (cok && row < R) ? C[(size_t)row * lda + cb] : T(0);
+            const int row = min(rb * 16 + Mfma<T>::row_of(lq, r), R - 1);
+            acc[r] = C[(size_t)row * lda + col];
           }
+        };
+        int pp = wave, rb = 0, cb = 0;
+        acc_t cur;
+        if (pp < npair) load_c(pp, cur, rb, cb);
+        while (pp < npair) {
+          const int pn = pp + kWaves;
+          acc_t nxt;
+          int rbn = 0, cbn = 0;
+          if (pn < npair) load_c(pn, nxt, rbn, cbn);
           const int arow = nb + min(rb * 16 + li, R - 1);
 #pragma unroll
           for (int s4 = 0; s4 < NB / 4; ++s4) {
             const int k = 4 * s4 + lq;
-            acc = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + (cb & (kUC - 1))], acc);
+            cur = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + cb], cur);
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = rb * 16 + Mfma<T>::row_of(lq, r);
-            if (cok && row < R) C[(size_t)row * lda + cb] = acc[r];
+            if (cb < cw && row < R) C[(size_t)row * lda + cb] = cur[r];
           }
+          cur = nxt;
+          rb = rbn;
+          cb = cbn;
+          pp = pn;
         }
       }
       __syncthreads();
@@ -282,8 +360,17 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int32_t* 
   for (int i = tid; i < batch; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
 }
 
+// Waves per SIMD each instantiation is built for, i.e. resident workgroups
+// per CU (as many as the LDS allows) x 8 waves / 4 SIMDs: FP64 16 -> 2
+// workgroups, FP64 32 -> 1, FP32 16 -> 3, FP32 32 -> 2.  Registers are held to
+// it (the second launch bound is the minimum waves per execution unit).
 template <typename T, int NB>
-__global__ __launch_bounds__(kBT) void k_getrf_batched(int batch, const int32_t* __restrict__ d_n, T* const* d_A,
+constexpr int batched_min_blocks() {
+  return (sizeof(T) == 8 ? (NB == 16 ? 2 : 1) : (NB == 16 ? 3 : 2)) * (kBT / kWave) / 4;
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kBT, (batched_min_blocks<T, NB>())) void k_getrf_batched(int batch, const int32_t* __restrict__ d_n, T* const* d_A,
                                                        const int32_t* __restrict__ d_lda, int32_t* const* d_ipiv,
                                                        int32_t* __restrict__ d_info, int max_n,
                                                        const int32_t* __restrict__ order, unsigned* queue) {
