@@ -139,3 +139,54 @@ def test_batched_graph_replays_match_eager():
         assert torch.equal(plan.ipiv, ref_piv), rep
         for w, r in zip(work, ref):
             assert torch.equal(w, r), rep
+
+
+def _bench_batch(dt, count=20000):
+    """The bench's batched workload: orders n ~ U{8..512} (seed 0), each
+    A = B B^T + n I with B ~ N(0, 1) drawn on the device per order (seed 1)."""
+    rng = np.random.default_rng(0)
+    ns = rng.integers(8, 513, count)
+    offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
+    buf = torch.empty(int(offs[-1]), dtype=dt, device=DEV)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(1)
+    for n in np.unique(ns):
+        idx = np.nonzero(ns == n)[0]
+        b = torch.randn(len(idx), int(n), int(n), generator=g, dtype=torch.float64, device=DEV)
+        a = torch.bmm(b, b.transpose(1, 2).contiguous())
+        a.diagonal(dim1=1, dim2=2).add_(float(n))
+        for t, i in enumerate(idx):
+            buf[int(offs[i]):int(offs[i + 1])].copy_(a[t].reshape(-1))
+        del a, b
+    mats = [buf[int(offs[i]):int(offs[i + 1])].view(int(n), int(n)) for i, n in enumerate(ns)]
+    return ns, buf, mats
+
+
+@pytest.mark.parametrize("dt,nb", [(torch.float64, 16), (torch.float64, 32), (torch.float32, 32)])
+def test_batched_full_bench_configuration(dt, nb):
+    """The full 20 000-matrix launch the bench times: every info code, and 120
+    sampled matrices (the largest and smallest orders included) against the
+    oracle (FP64: pivots identical, factors within 1e-12 * max|F|) or by
+    residual and legal pivots (FP32)."""
+    ns, buf, mats = _bench_batch(dt)
+    rng = np.random.default_rng(7)
+    pick = sorted(set(rng.choice(len(ns), 118, replace=False).tolist()) | {int(ns.argmax()), int(ns.argmin())})
+    before = {i: mats[i].double().cpu().numpy() for i in pick}
+    plan = mlu.BatchPlan(mats, max_n=512, nb=nb)
+    plan.run()
+    info = host(plan.info)
+    assert (info == 0).all()
+    for i in pick:
+        a = before[i]
+        F = host(mats[i]).astype(np.float64)
+        piv = (host(plan.pivots(i)) - 1).tolist()
+        if dt == torch.float64:
+            R = a.copy()
+            opiv, oinfo = O.getrf(R, "rl", nb=32)
+            assert piv == opiv, (i, a.shape[0])
+            assert np.abs(F - R).max() <= 1e-12 * np.abs(R).max(), (i, a.shape[0])
+        else:
+            assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-5, (i, a.shape[0])
+            assert np.abs(np.tril(F, -1)).max() <= 1.0
+    del plan, mats, buf
+    torch.cuda.empty_cache()
