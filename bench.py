@@ -264,7 +264,7 @@ def selector_section(args):
 
 
 def mixed_section(args, dev):
-    """FP32-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
+    """FP32- and BF16-product LU + FP64 refinement (mlu_dsgesv_ir) against the plain FP64
     solve (the same entry point with FP64 products and no correction: getrf,
     getrs, one residual) on A = Q diag(sv) Q^T, Q Haar, for several condition
     numbers; one right-hand side b ~ N(0, 1).  Both timed with HIP events on
@@ -312,25 +312,28 @@ def mixed_section(args, dev):
             out["r64"] = mlu.gesv_ir(A, b, precision="fp64", tol=1e-13, max_iter=0, variant=args.variant,
                                      nb=args.nb, nb_inner=args.nb_inner, X=x64, work=work_ir)
 
-        def mixedrun():
-            out["r"] = mlu.gesv_ir(A, b, precision="fp32", tol=1e-13, max_iter=10, variant=args.variant, nb=args.nb,
-                                   nb_inner=args.nb_inner, X=xmp, work=work_ir)
-
         fp64()   # warm-up
-        mixedrun()
         t64 = timed(fp64)
-        tmp = timed(mixedrun)
-        _, _, minfo, iters, berr = out["r"]
-        case = {"cond": cond, "ms_fp64_solve": round(t64, 3), "ms_mixed_ir": round(tmp, 3),
-                "speedup": round(t64 / tmp, 3), "iters": int(iters.item()), "berr": float(berr.item()),
-                "berr_fp64_solve": float(out["r64"][4].item()), "berr_fp64_recomputed": berr_of(A, x64),
-                "berr_recomputed": berr_of(A, xmp), "info": int(minfo.item()),
-                "rel_diff_vs_fp64_solve": float((xmp - x64).abs().max() / x64.abs().max())}
-        log(f"mixed cond={cond:g}: {case}")
-        cases.append(case)
+        for low, max_iter in (("fp32", 10), ("bf16", 30)):
+            def mixedrun():
+                out["r"] = mlu.gesv_ir(A, b, precision=low, tol=1e-13, max_iter=max_iter, variant=args.variant,
+                                       nb=args.nb, nb_inner=args.nb_inner, X=xmp, work=work_ir)
+
+            mixedrun()   # warm-up
+            tmp = timed(mixedrun)
+            _, _, minfo, iters, berr = out["r"]
+            case = {"cond": cond, "precision": low, "max_iter": max_iter, "ms_fp64_solve": round(t64, 3),
+                    "ms_mixed_ir": round(tmp, 3), "speedup": round(t64 / tmp, 3), "iters": int(iters.item()),
+                    "berr": float(berr.item()), "berr_fp64_solve": float(out["r64"][4].item()),
+                    "berr_fp64_recomputed": berr_of(A, x64), "berr_recomputed": berr_of(A, xmp),
+                    "info": int(minfo.item()),
+                    "rel_diff_vs_fp64_solve": float((xmp - x64).abs().max() / x64.abs().max())}
+            log(f"mixed cond={cond:g} {low}: {case}")
+            cases.append(case)
         del A
-    return {"what": "FP32-product trailing updates (FP64 panel, solves, residual, correction) + FP64 "
-                    "iterative refinement to backward error <= 1e-13, vs the FP64 solve (getrf + getrs + residual)",
+    return {"what": "FP32- and BF16-product trailing updates (FP32 accumulation; FP64 panel, solves, residual, "
+                    "correction) + FP64 iterative refinement to backward error <= 1e-13, vs the FP64 solve "
+                    "(getrf + getrs + residual)",
             "n": n, "nrhs": 1, "matrix": "Q diag(logspace(0,-log10 cond,n)) Q^T, Q Haar (seed 0), b ~ N(0,1)",
             "cases": cases}
 

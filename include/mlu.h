@@ -52,14 +52,16 @@ enum mlu_variant {
 /*
  * Precision of the products in the outer trailing updates (RL3, PF2, RU2, LL2)
  * of the mixed-precision factorization.  The matrix stays FP64 in memory: the
- * operands of each update are rounded to the lower precision, the product is
- * accumulated in it (FP32 matrix cores), and it is subtracted from the FP64
- * trailing matrix.  The panel factorization and its inner updates, the
- * triangular solves and the interchanges stay FP64.
+ * operands of each update are rounded to the lower precision (FP32, or BF16
+ * through FP32 with round to nearest even), the product is accumulated in FP32
+ * on the matrix cores, and it is subtracted from the FP64 trailing matrix.  The
+ * panel factorization and its inner updates, the triangular solves and the
+ * interchanges stay FP64.
  */
 enum mlu_precision {
   MLU_PREC_FP64 = 0,
-  MLU_PREC_FP32 = 1
+  MLU_PREC_FP32 = 1,
+  MLU_PREC_BF16 = 2  /* BF16 operands, FP32 accumulation */
 };
 
 /* Largest order of a matrix in the batched factorization. */
@@ -154,9 +156,10 @@ int mlu_dgetrf_et(void *stream, int m, int n, double *dA, int lda, int32_t *d_ip
 
 /*
  * Mixed-precision LU with partial pivoting: mlu_dgetrf with the outer trailing
- * updates' products in `precision` (MLU_PREC_FP32, or MLU_PREC_FP64 for
- * exactly mlu_dgetrf).  The factors are those of a matrix within about
- * u_low * ||A|| of A (u_low = 2^-24 for FP32) rather than u_64 * ||A||: meant
+ * updates' products in `precision` (MLU_PREC_FP32, MLU_PREC_BF16, or
+ * MLU_PREC_FP64 for exactly mlu_dgetrf).  The factors are those of a matrix
+ * within about u_low * ||A|| of A (u_low = 2^-24 for FP32, 2^-8 for BF16)
+ * rather than u_64 * ||A||: meant
  * as the factorization inside iterative refinement (mlu_dsgesv_ir), the
  * precision ladder the paper's loop-based variants admit unchanged (Fig.
  * "LU", Fig. "LU_la_blk": only the update kernel differs).  Arguments as

@@ -24,6 +24,8 @@
 //    panels at a time.
 #include "mlu_internal.h"
 
+#include <hip/hip_bf16.h>
+
 #include <mutex>
 #include <vector>
 
@@ -432,12 +434,132 @@ __device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, in
       }
 }
 
+// The same 128 x 128 tile with BF16 operands and FP32 accumulation: A and B
+// are rounded to BF16 as they are staged into LDS (through FP32, round to
+// nearest even), v_mfma_f32_16x16x16bf16_1k takes one 16-deep K stage per
+// MFMA, and the epilogue subtracts the FP32 product from the FP64 C.  B is kept
+// transposed in LDS so that each lane's four K values are contiguous.  Lane
+// layout (checked on gfx950): A element (i, k) from lane i + 16 q, slot s with
+// k = 4 q + s; B element (k, j) from lane j + 16 q, slot s; D rows 4 q + r of
+// column j in lane j + 16 q.
+typedef short v4bf __attribute__((ext_vector_type(4)));
+constexpr int LDSH_A = BK + 8;   // bf16 per A row in LDS (48 bytes)
+constexpr int LDSH_B = BK + 8;   // bf16 per transposed-B row in LDS
+
+__device__ __forceinline__ unsigned short to_bf16(double x) {
+  const __hip_bfloat16 h = __float2bfloat16((float)x);
+  return *reinterpret_cast<const unsigned short*>(&h);
+}
+
+template <bool VEC>
+__device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                               int lda, const double* __restrict__ B, int ldb,
+                                               double* __restrict__ C, int ldc) {
+  __shared__ __attribute__((aligned(16))) unsigned short Ash[2][BM * LDSH_A];
+  __shared__ __attribute__((aligned(16))) unsigned short Bth[2][BN * LDSH_B];
+
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ar = tid >> 1, ac = (tid & 1) * 8;
+  const int br = tid >> 4, bc = (tid & 15) * 8;
+  const bool interior_mn = (row0 + BM <= m) && (col0 + BN <= n);
+
+  double ra[8], rb[8];
+  auto gload = [&](int k0) {
+    const bool full = VEC && interior_mn && (k0 + BK <= k);
+    if (full) {
+      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double2 x = pa[e];
+        ra[2 * e] = x.x;
+        ra[2 * e + 1] = x.y;
+        const double2 y = pb[e];
+        rb[2 * e] = y.x;
+        rb[2 * e + 1] = y.y;
+      }
+    } else {
+      const int gr = row0 + ar;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + ac + e;
+        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
+      const int gk = k0 + br;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gc = col0 + bc + e;
+        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+    unsigned short ha[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ha[e] = to_bf16(ra[e]);
+    uint4 pk;
+    pk.x = ha[0] | ((unsigned)ha[1] << 16);
+    pk.y = ha[2] | ((unsigned)ha[3] << 16);
+    pk.z = ha[4] | ((unsigned)ha[5] << 16);
+    pk.w = ha[6] | ((unsigned)ha[7] << 16);
+    *reinterpret_cast<uint4*>(&Ash[buf][ar * LDSH_A + ac]) = pk;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Bth[buf][(bc + e) * LDSH_B + br] = to_bf16(rb[e]);
+  };
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (k + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    v4bf a[4], b[4];
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+      a[blk] = *reinterpret_cast<const v4bf*>(&Ash[buf][(wm * 64 + blk * 16 + li) * LDSH_A + 4 * lq]);
+      b[blk] = *reinterpret_cast<const v4bf*>(&Bth[buf][(wn * 64 + blk * 16 + li) * LDSH_B + 4 * lq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  double* const cbase = C + (size_t)(row0 + wm * 64 + 4 * lq) * ldc + col0 + wn * 64 + li;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 64 + i * 16 + 4 * lq + r;
+        const int col = col0 + wn * 64 + j * 16 + li;
+        if (interior_mn || (row < m && col < n)) {
+          double* pc = cbase + (size_t)(i * 16 + r) * ldc + j * 16;
+          *pc = *pc - (double)acc[i][j][r];
+        }
+      }
+}
+
 // one tile in the requested product precision
 template <bool VEC, int PREC>
 __device__ __forceinline__ void tile_any(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
                                          int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
                                          int ldc) {
   if constexpr (PREC == kPrecF32) gemm_tile_f32<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  else if constexpr (PREC == kPrecBF16) gemm_tile_bf16<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
   else gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
@@ -546,7 +668,7 @@ void trace_slot(int m, int n, int k, hipEvent_t* e0, hipEvent_t* e1) {
 hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                        double* C, int ldc, bool trailing, int prec, bool traced, const int32_t* skip) {
   if (skip != nullptr && trailing) return hipErrorInvalidValue;
-  if (prec != kPrecF64 && prec != kPrecF32) return hipErrorInvalidValue;
+  if (prec != kPrecF64 && prec != kPrecF32 && prec != kPrecBF16) return hipErrorInvalidValue;
   if (prec != kPrecF64 && !trailing) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
   const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
@@ -573,6 +695,9 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
     if (prec == kPrecF32) {
       if (vec) hipLaunchKernelGGL((k_gemm_trailing<true, kPrecF32>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
       else hipLaunchKernelGGL((k_gemm_trailing<false, kPrecF32>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+    } else if (prec == kPrecBF16) {
+      if (vec) hipLaunchKernelGGL((k_gemm_trailing<true, kPrecBF16>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
+      else hipLaunchKernelGGL((k_gemm_trailing<false, kPrecBF16>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
     } else {
       if (vec) hipLaunchKernelGGL((k_gemm_trailing<true, kPrecF64>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
       else hipLaunchKernelGGL((k_gemm_trailing<false, kPrecF64>), grid, block, 0, s, m, n, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n);
@@ -589,7 +714,7 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                       double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
                       int prec) {
-  if (prec != kPrecF64 && prec != kPrecF32) return hipErrorInvalidValue;
+  if (prec != kPrecF64 && prec != kPrecF32 && prec != kPrecBF16) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) {
     if (clear == nullptr) return hipSuccess;
     m = n = k = 0;   // still clear the next slot
@@ -623,6 +748,13 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
                          ldc, tiles_m, tiles_n, q, clear, reserve);
     else
       hipLaunchKernelGGL((k_gemm_queue<false, kPrecF32>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+  } else if (prec == kPrecBF16) {
+    if (vec)
+      hipLaunchKernelGGL((k_gemm_queue<true, kPrecBF16>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
+                         ldc, tiles_m, tiles_n, q, clear, reserve);
+    else
+      hipLaunchKernelGGL((k_gemm_queue<false, kPrecBF16>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
                          ldc, tiles_m, tiles_n, q, clear, reserve);
   } else {
     if (vec)

@@ -385,7 +385,7 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
   if (variant < MLU_RL || variant > MLU_LA) return -8;
   if (nb < 1) return -9;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
-  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32) return -11;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -11;
   if (h_schedule) {
     if (n_schedule < 1) return -12 - sh;
     for (int i = 0; i < n_schedule; ++i)
@@ -415,7 +415,7 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
   }
   unsigned epoch = 0;
   Workspace* ws = reinterpret_cast<Workspace*>(d_work);
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, precision == MLU_PREC_FP32 ? kPrecF32 : kPrecF64,
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, precision == MLU_PREC_FP32 ? kPrecF32 : (precision == MLU_PREC_BF16 ? kPrecBF16 : kPrecF64),
         &epoch};
   c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
 

@@ -236,7 +236,7 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
   if (ldb < (nrhs > 1 ? nrhs : 1)) return -7;
   if (n > 0 && nrhs > 0 && !dX) return -8;
   if (ldx < (nrhs > 1 ? nrhs : 1)) return -9;
-  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32) return -10;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -10;
   if (!(tol >= 0.0)) return -11;
   if (max_iter < 0) return -12;
   if (variant < MLU_RL || variant > MLU_LA) return -13;

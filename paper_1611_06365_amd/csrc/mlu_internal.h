@@ -80,8 +80,10 @@ size_t workspace_bytes();
 // it, and C stays FP64.
 constexpr int kPrecF64 = 0;
 constexpr int kPrecF32 = 1;
+constexpr int kPrecBF16 = 2;   // BF16 operands, FP32 accumulation
 
-// `trailing` selects the trailing-update kernel (and allows prec = kPrecF32);
+// `trailing` selects the trailing-update kernel (and allows prec = kPrecF32 or
+// kPrecBF16);
 // `traced` lets a trailing launch record events while a trace is active.
 // `skip` (device flag, may be null; generic kernel only): when it reads
 // nonzero the launch does nothing.

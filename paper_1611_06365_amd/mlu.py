@@ -19,8 +19,8 @@ MLU_ERR_HIP = -1000
 MLU_INFO_SYNC_TIMEOUT = -999
 MLU_INFO_BAD_PIVOT = -998
 MLU_MAX_NB_INNER = 16
-MLU_PREC_FP64, MLU_PREC_FP32 = 0, 1
-PRECISION_IDS = {"fp64": MLU_PREC_FP64, "fp32": MLU_PREC_FP32}
+MLU_PREC_FP64, MLU_PREC_FP32, MLU_PREC_BF16 = 0, 1, 2
+PRECISION_IDS = {"fp64": MLU_PREC_FP64, "fp32": MLU_PREC_FP32, "bf16": MLU_PREC_BF16}
 
 _vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
 

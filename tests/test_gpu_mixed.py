@@ -161,3 +161,43 @@ def test_gesv_ir_zero_iterations_and_empty():
     b = torch.zeros((0, 1), dtype=torch.float64, device=DEV)
     X, ipiv, info, iters, berr = mlu.gesv_ir(e, b)
     assert int(host(info)[0]) == 0 and int(host(iters)[0]) == 0 and float(host(berr)[0]) == 0.0
+
+
+@pytest.mark.parametrize("variant", ["rl", "la"])
+@pytest.mark.parametrize("recipe,n", [("spd", 1024), ("haar", 777)])
+def test_dsgetrf_bf16_factors(variant, recipe, n):
+    # BF16 operands (u = 2^-8), FP32 accumulation: the factors are those of a
+    # matrix within a few u_bf16 of A, and clearly not FP32-accurate
+    A = {"spd": lambda: G.spd_bbt(n, seed=3), "haar": lambda: G.haar_spectrum(n, 1e4, seed=3)}[recipe]()
+    dA = dev(A)
+    ipiv, info = mlu.getrf(dA, variant=variant, nb=128, precision="bf16")
+    F = host(dA)
+    assert int(host(info)[0]) == 0
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    res = np.linalg.norm(A[perm_rows(host(ipiv), n)] - L @ U) / np.linalg.norm(A)
+    print(f"dsgetrf bf16 {recipe} n={n} {variant}: residual {res:.2e}", flush=True)
+    assert res <= 3e-2
+    assert res > 1e-5, "the trailing products do not look like BF16"
+    assert np.abs(np.tril(F, -1)).max() <= 1.0
+
+
+@pytest.mark.parametrize("variant", ["rl", "la"])
+def test_gesv_ir_bf16_reaches_fp64_backward_error(variant):
+    # kappa * u_bf16 ~ 0.4: LU-IR converges, slowly; the same bars as FP32
+    n = 640
+    A = G.haar_spectrum(n, 1e2, seed=7)
+    B = G.gaussian_rhs(n, 2, seed=1)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dev(A), dev(B), precision="bf16", tol=1e-13, max_iter=60,
+                                             variant=variant, nb=64)
+    Xh = host(X)
+    it, be = int(host(iters)[0]), float(host(berr)[0])
+    hb = backward_error(A, Xh, B)
+    X64 = oracle_solution(("bf16", 1e2), A, B)
+    fwd = np.abs(Xh - X64).max() / np.abs(X64).max()
+    print(f"gesv_ir bf16 cond=1e2 {variant}: iters {it}, berr {be:.2e} (host {hb:.2e}), |x - x64|/|x64| {fwd:.2e}",
+          flush=True)
+    assert int(host(info)[0]) == 0
+    assert 0 <= it <= 60
+    assert be <= 1e-13 and hb <= 2e-13
+    assert fwd <= 1e2 * 1e-12
