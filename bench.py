@@ -232,6 +232,47 @@ def et_section(args, A, ipiv, info, work):
             "n": A.shape[0], "matrix": args.matrix, "rows": rows}
 
 
+def grid_section(args, dev):
+    """Every variant at n in {4096, 8192, 16384} and nb in {64, 128, 256} (b_i =
+    16) on A = B B^T + n I (seed 0): one warm-up, then the best of two timed
+    factorizations (HIP events), each on a fresh copy restored outside the
+    timed region."""
+    import torch
+
+    import inputs.device as D
+    from paper_1611_06365_amd import mlu
+
+    rows = []
+    work = mlu.workspace(dev)
+    for n in (4096, 8192, 16384):
+        A = D.spd_bbt(n, seed=0, device=dev)
+        M = torch.empty_like(A)
+        ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        for variant in ("rl", "ll", "la"):
+            for nb in (64, 128, 256):
+                best = None
+                for r in range(3):
+                    M.copy_(A)
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    mlu.getrf(M, variant=variant, nb=nb, nb_inner=16, ipiv=ipiv, info=info, work=work)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    if r > 0:
+                        t = e0.elapsed_time(e1)
+                        best = t if best is None else min(best, t)
+                gf = 2.0 * n ** 3 / 3.0 / (best / 1e3) / 1e9
+                row = {"n": n, "variant": variant, "nb": nb, "ms": round(best, 3), "gflops": round(gf, 1),
+                       "frac_fp64_peak": round(gf / (FP64_PEAK_TFLOPS * 1e3), 4), "info": int(info.item())}
+                log(f"grid: {row}")
+                rows.append(row)
+        del A, M
+        torch.cuda.empty_cache()
+    return rows
+
+
 def selector_section(args):
     """The learned selector: its choice for the bench workload, its inference
     latency through the C ABI (mlu_select) and in Python, and the regret on
@@ -355,6 +396,8 @@ def main() -> int:
     ap.add_argument("--mixed-conds", default="1e2,1e5,1e8")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
     ap.add_argument("--no-et", action="store_true", help="skip the early-termination comparison")
+    ap.add_argument("--grid", action="store_true",
+                    help="also time every variant at n in {4096, 8192, 16384} x nb in {64, 128, 256}")
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
@@ -456,6 +499,8 @@ def main() -> int:
 
     sel = selector_section(args)
 
+    grid = grid_section(args, dev) if args.grid else None
+
     et = None
     if not args.no_et:
         et = et_section(args, A, ipiv, info, work)
@@ -504,6 +549,7 @@ def main() -> int:
         "mixed": mixed,
         "early_termination": et,
         "selector": sel,
+        "grid": grid,
         "batched": batched,
         "cpu_baseline": cpu,
         "check": check,
