@@ -124,7 +124,7 @@ int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv,
 
 /*
  * LU with partial pivoting by the look-ahead variant with early termination of
- * the panel factorization (Section 4.3, "Early termination"; Fig.
+ * the panel factorization (Section 4.2, "Early termination"; Fig.
  * "LU_LA_ET").  Each look-ahead panel PF3 is factored by the blocked
  * left-looking algorithm in nb_inner-wide blocks, which touches nothing to the
  * right of the current block; when the trailing update RU2 of the same outer
@@ -227,7 +227,7 @@ int mlu_sgetrf_batched(void *stream, int batch, const int32_t *d_n, float *const
                        size_t work_bytes);
 
 /*
- * The learned selector (the block-size study of Section 5 as a model): given
+ * The learned selector (the block-size study of Section 5.1 as a model): given
  * the order n and the product precision, choose the variant and the outer
  * block size b for mlu_dgetrf / mlu_dsgetrf.  Host function, no device work.
  *  model       host float array written by the selector's pack(): header

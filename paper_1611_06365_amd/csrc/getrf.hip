@@ -14,6 +14,9 @@
 //  LL  (Section 4.2)           lazy interchanges of the panel columns, LL1 trsm
 //                              and LL2 gemm block by block, LL3 panel,
 //                              interchanges of the left columns
+//  LA with early termination   LA whose PF3 is a left-looking inner LU that
+//  (Section 4.2, Fig.          stops when RU2 signals; the width it reached
+//  "LU_LA_ET")                 is the next block size
 //
 // The panel [A11; A21] is itself factored by the blocked RL algorithm with the
 // inner block size b_i <= 16, each b_i-wide block by the register-resident
@@ -38,7 +41,7 @@ __global__ void k_et_signal(unsigned* ru_done, unsigned k1) {
   if (threadIdx.x == 0) __hip_atomic_store(ru_done, k1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// End of one inner iteration of the look-ahead panel (Section 4.3, early
+// End of one inner iteration of the look-ahead panel (Section 4.2, early
 // termination): unless the panel has already stopped, it now covers `cols`
 // columns; it stops once RU2 of the current outer iteration has signalled.
 // The flag is read once per inner iteration, so every later launch of the
@@ -245,7 +248,7 @@ hipError_t run_ll(hipStream_t s, const Ctx& c, const std::vector<int>& sched, in
 
 // PF3 / the initial panel of the early-termination variant: the panel rows
 // j..m-1, columns j..j+b-1, factored by the blocked left-looking algorithm
-// with b_i-wide blocks (Section 4.3): before block [jj, jj+bw) it receives the
+// with b_i-wide blocks (Section 4.2): before block [jj, jj+bw) it receives the
 // panel's earlier interchanges (lazy), LL1 solves its rows j..jj-1 with the
 // panel's unit lower triangle, LL2 updates its rows jj.. with the panel's
 // columns to its left, LL3 factors it (interchanges applied to the panel's
@@ -274,7 +277,7 @@ hipError_t factor_panel_ll(hipStream_t s, const Ctx& c, int j, int b, EtWork* et
   return hipSuccess;
 }
 
-// Look-ahead with early termination of the panel factorization (Section 4.3,
+// Look-ahead with early termination of the panel factorization (Section 4.2,
 // Fig. "LU_LA_ET"): as run_la, with PF3 the left-looking inner LU above and
 // a signal after RU2.  The host waits once per outer iteration for the width
 // the panel reached (the next iteration's b); `force` = 1 stops every

@@ -1,5 +1,5 @@
 // Host-side evaluation of the learned selector (variant and block size from
-// the problem size; the block-size study of Section 5 turned into a model):
+// the problem size; the block-size study of Section 5.1 turned into a model):
 // a multilayer perceptron in FP32 whose outputs are the predicted
 // log time per flop of every configuration; the smallest wins.
 #include "../../include/mlu.h"

@@ -1,5 +1,5 @@
 """Choosing the variant and block size: an exhaustive autotuner and a learned
-selector (the block-size study of Section 5, where the best b_o depends on the
+selector (the block-size study of Section 5.1, where the best b_o depends on the
 algorithm and the problem size, turned into a model).
 
 * `collect` is the exhaustive autotuner: it times every configuration of

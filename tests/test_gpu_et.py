@@ -1,5 +1,5 @@
 """GPU parity of the look-ahead LU with early termination of the panel
-(mlu_dgetrf_et, Section 4.3): the realized panel widths are a schedule, and
+(mlu_dgetrf_et, Section 4.2): the realized panel widths are a schedule, and
 the factorization must be the oracle's look-ahead LU with that schedule and a
 left-looking inner LU of the same block size.
 
