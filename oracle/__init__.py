@@ -10,4 +10,4 @@ from .lu import (  # noqa: F401
     trsm_unit_lower, unpack, permutation_of, apply_interchanges, schedule_from,
     flops_lu_exact, iamax_first,
 )
-from . import invariants  # noqa: F401
+from . import invariants, refine  # noqa: F401
