@@ -196,6 +196,44 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
                   size_t work_bytes);
 
 /*
+ * Solve A x = b (one right-hand side) by mixed-precision LU and FP64
+ * refinement whose corrections may come from GMRES (GMRES-IR: Carson and
+ * Higham, SIAM J. Sci. Comput. 2017 and 2018), for kappa(A) * u_low >~ 1,
+ * where the plain corrections of mlu_dsgesv_ir stop converging.  M = P^T L U is
+ * the factorization of mlu_dsgetrf(precision, variant, nb, nb_inner) (Section 3),
+ * applied in FP64 as the preconditioner.
+ *   x := M^-1 b;
+ *   repeat: r := b - A x in FP64;
+ *           berr := ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf);
+ *           stop if berr <= tol (or after max_outer corrections);
+ *           solver MLU_IR_LU:    d := M^-1 r;
+ *           solver MLU_IR_GMRES: d := GMRES on M^-1 A d = M^-1 r from d = 0,
+ *             Arnoldi with classical Gram-Schmidt applied twice, Givens
+ *             rotations; it stops when its residual estimate falls to
+ *             gmres_tol * ||M^-1 r||_2, at max_krylov steps, or at a breakdown;
+ *           solver MLU_IR_AUTO:  MLU_IR_LU while each correction at least
+ *             halves berr, MLU_IR_GMRES from the first one that does not;
+ *           x := x + d.
+ *  dA (n x n, lda), db (n): read only.  dx (n): the solution.  d_ipiv and
+ *  d_info as mlu_dgetrf, for the factors.  On return (the call waits for the
+ *  stream once per outer and per GMRES step, so it is not capturable):
+ *  *h_outer = corrections applied when berr <= tol was reached (0 if the first
+ *  solve met it), or -1 if max_outer corrections did not reach it;
+ *  *h_inner = GMRES steps over all corrections; *h_berr = berr of the x
+ *  returned.  1 <= max_krylov <= MLU_GMRES_MAX_KRYLOV; n <= 32768.
+ *  d_work: mlu_dsgesv_gmres_ir_workspace(n, max_krylov) bytes (the n x n
+ *  factors and the Krylov basis).  Returns 0, -i for an invalid argument i,
+ *  or MLU_ERR_HIP.
+ */
+enum mlu_ir_solver { MLU_IR_LU = 0, MLU_IR_GMRES = 1, MLU_IR_AUTO = 2 };
+#define MLU_GMRES_MAX_KRYLOV 512
+int mlu_dsgesv_gmres_ir_workspace(int n, int max_krylov, size_t *bytes);
+int mlu_dsgesv_gmres_ir(void *stream, int n, const double *dA, int lda, const double *db, double *dx,
+                        int precision, int solver, double tol, int max_outer, int max_krylov, double gmres_tol,
+                        int variant, int nb, int nb_inner, int32_t *d_ipiv, int32_t *d_info, int32_t *h_outer,
+                        int32_t *h_inner, double *h_berr, void *d_work, size_t work_bytes);
+
+/*
  * Batched LU with partial pivoting of `batch` independent square matrices of
  * different orders, in one persistent launch (Section 3 applied to each
  * operand: blocked right-looking with an unblocked panel, Fig. "LU").

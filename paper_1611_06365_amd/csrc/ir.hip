@@ -12,6 +12,8 @@
 namespace mlu {
 namespace {
 
+constexpr int kGmresMaxKrylov = MLU_GMRES_MAX_KRYLOV;
+
 // refinement state in the workspace (non-negative doubles as their bit
 // patterns, so that the maxima can be taken with integer atomics)
 struct IrState {
@@ -209,6 +211,143 @@ unsigned grid_for(size_t work) {
   return (unsigned)(g > 0 ? g : 1);
 }
 
+
+// ---------------------------------------------------------------- GMRES-IR
+// Correction equation M^-1 A d = M^-1 r solved by GMRES (Carson and Higham's
+// GMRES-IR; GMRES of Saad and Schultz), M = P^T L U the low-precision factors
+// applied in FP64 by getrs_blocked.  The Krylov basis V is (m+1) vectors of n
+// doubles, vector j at V + j * n; Arnoldi orthogonalizes against it by
+// classical Gram-Schmidt applied twice (two rounds of dot products and one
+// update each, instead of k dependent steps of modified Gram-Schmidt); H is
+// kept column by column (column k at H + k * (m + 1)) and reduced by Givens
+// rotations as it grows.  Every reduction runs in a fixed order, so results do
+// not depend on scheduling.
+struct GmresState {
+  unsigned long long anorm, bnorm, xnorm, rnorm;   // bit patterns of non-negative doubles
+  double berr;    // backward error of the current x
+  double beta;    // ||z||_2 of the current correction's right-hand side
+  double hnext;   // h(k+1, k) of the last Arnoldi step, before its rotation
+  double resid;   // |g(k+1)|: GMRES residual norm after the last step
+};
+
+// out[j] = V_j . w for j < k (one workgroup per j, fixed-order reduction)
+__global__ __launch_bounds__(256) void k_dots(int n, int k, const double* __restrict__ V, const double* __restrict__ w,
+                                              double* __restrict__ out) {
+  __shared__ double part[4];
+  const int j = blockIdx.x;
+  if (j >= k) return;
+  const double* v = V + (size_t)j * n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += v[i] * w[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[j] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// w[i] += sign * sum_{j<k} V_j[i] h[j]  (the sum first, then one update)
+__global__ __launch_bounds__(256) void k_basis_combine(int n, int k, const double* __restrict__ V,
+                                                       const double* __restrict__ h, double sign,
+                                                       double* __restrict__ w) {
+  __shared__ double hs[kGmresMaxKrylov + 1];
+  for (int j = threadIdx.x; j < k; j += 256) hs[j] = h[j];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s += V[(size_t)j * n + i] * hs[j];
+  w[i] = w[i] + sign * s;
+}
+
+// v[i] := v[i] / *div
+__global__ void k_div_by(int n, double* __restrict__ v, const double* __restrict__ div) {
+  const double d = *div;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = v[i] / d;
+}
+
+// one thread: beta = sqrt(z . z), g = (beta, 0, ..., 0)
+__global__ void k_gmres_start(GmresState* st, const double* __restrict__ zz, double* __restrict__ g, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double beta = sqrt(*zz);
+  st->beta = beta;
+  g[0] = beta;
+  for (int i = 1; i <= m; ++i) g[i] = 0.0;
+}
+
+// one thread: Arnoldi step k's column of H from the two Gram-Schmidt rounds
+// (h1 + h2) and ||w||_2, the earlier rotations applied to it, a new rotation
+// that zeroes h(k+1, k), and the rotated right-hand side g.
+__global__ void k_arnoldi(GmresState* st, int k, int m, const double* __restrict__ h1, const double* __restrict__ h2,
+                          const double* __restrict__ ww, double* __restrict__ H, double* __restrict__ cs,
+                          double* __restrict__ sn, double* __restrict__ g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + (size_t)k * (m + 1);
+  for (int j = 0; j <= k; ++j) col[j] = h1[j] + h2[j];
+  const double hnext = sqrt(*ww);
+  st->hnext = hnext;
+  for (int j = 0; j < k; ++j) {
+    const double a = col[j], b = col[j + 1];
+    col[j] = cs[j] * a + sn[j] * b;
+    col[j + 1] = -sn[j] * a + cs[j] * b;
+  }
+  const double a = col[k], b = hnext;
+  const double rho = hypot(a, b);
+  const double c = rho == 0.0 ? 1.0 : a / rho;
+  const double s = rho == 0.0 ? 0.0 : b / rho;
+  cs[k] = c;
+  sn[k] = s;
+  col[k] = rho;
+  col[k + 1] = 0.0;
+  g[k + 1] = -s * g[k];
+  g[k] = c * g[k];
+  st->resid = fabs(g[k + 1]);
+}
+
+// one thread: y = R^-1 g over the first `steps` columns of the rotated H
+__global__ void k_hess_solve(int steps, int m, const double* __restrict__ H, const double* __restrict__ g,
+                             double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = steps - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int j = i + 1; j < steps; ++j) t -= H[(size_t)j * (m + 1) + i] * y[j];
+    y[i] = t / H[(size_t)i * (m + 1) + i];
+  }
+}
+
+// one thread: berr of the current x from the maxima, and their reset
+__global__ void k_gmres_berr(GmresState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double den = bitsd(st->anorm) * bitsd(st->xnorm) + bitsd(st->bnorm);
+  const double rn = bitsd(st->rnorm);
+  st->berr = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+  st->xnorm = 0ull;
+  st->rnorm = 0ull;
+}
+
+struct GmresLayout {
+  size_t lu, linv, uinv, r, t, v, h, cs, sn, g, y, dots, state, total;
+};
+GmresLayout gmres_layout(int n, int m) {
+  GmresLayout L;
+  const size_t inv = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(double);
+  const size_t vec = (size_t)n * sizeof(double), small = (size_t)(m + 2) * sizeof(double);
+  L.lu = align_up(workspace_bytes());
+  L.linv = align_up(L.lu + (size_t)n * n * sizeof(double));
+  L.uinv = align_up(L.linv + inv);
+  L.r = align_up(L.uinv + inv);
+  L.t = align_up(L.r + vec);
+  L.v = align_up(L.t + vec);
+  L.h = align_up(L.v + (size_t)(m + 1) * vec);
+  L.cs = align_up(L.h + (size_t)m * (m + 1) * sizeof(double));
+  L.sn = align_up(L.cs + small);
+  L.g = align_up(L.sn + small);
+  L.y = align_up(L.g + small);
+  L.dots = align_up(L.y + small);
+  L.state = align_up(L.dots + 3 * small);
+  L.total = align_up(L.state + sizeof(GmresState));
+  return L;
+}
+
 }  // namespace
 }  // namespace mlu
 
@@ -303,6 +442,173 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   }
   return 0;
+}
+
+}  // extern "C"
+
+namespace {
+
+// the host's copy of the refinement state, after the stream has reached it
+hipError_t read_state(hipStream_t s, const GmresState* d, GmresState* h) {
+  MLU_IR_TRY(hipMemcpyAsync(h, d, sizeof(GmresState), hipMemcpyDeviceToHost, s));
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlu_dsgesv_gmres_ir_workspace(int n, int max_krylov, size_t* bytes) {
+  if (n < 0) return -1;
+  if (max_krylov < 1 || max_krylov > MLU_GMRES_MAX_KRYLOV) return -2;
+  if (!bytes) return -3;
+  *bytes = gmres_layout(n, max_krylov).total;
+  return 0;
+}
+
+int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const double* db, double* dx, int precision,
+                        int solver, double tol, int max_outer, int max_krylov, double gmres_tol, int variant, int nb,
+                        int nb_inner, int32_t* d_ipiv, int32_t* d_info, int32_t* h_outer, int32_t* h_inner,
+                        double* h_berr, void* d_work, size_t work_bytes) {
+  if (n < 0 || n > kPanelMaxRows) return -2;
+  if (n > 0 && !dA) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !db) return -5;
+  if (n > 0 && !dx) return -6;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -7;
+  if (solver != MLU_IR_LU && solver != MLU_IR_GMRES && solver != MLU_IR_AUTO) return -8;
+  if (!(tol >= 0.0)) return -9;
+  if (max_outer < 0) return -10;
+  if (max_krylov < 1 || max_krylov > MLU_GMRES_MAX_KRYLOV) return -11;
+  if (!(gmres_tol >= 0.0)) return -12;
+  if (variant < MLU_RL || variant > MLU_LA) return -13;
+  if (nb < 1) return -14;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -15;
+  if (n > 0 && !d_ipiv) return -16;
+  if (!d_info) return -17;
+  if (!h_outer) return -18;
+  if (!h_inner) return -19;
+  if (!h_berr) return -20;
+  if (!d_work) return -21;
+  const int m = max_krylov;
+  const GmresLayout L = gmres_layout(n, m);
+  if (work_bytes < L.total) return -22;
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  *h_outer = 0;
+  *h_inner = 0;
+  *h_berr = 0.0;
+  if (n == 0) {
+    if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : MLU_ERR_HIP;
+  }
+  char* base = reinterpret_cast<char*>(d_work);
+  double* LU = reinterpret_cast<double*>(base + L.lu);
+  double* Linv = reinterpret_cast<double*>(base + L.linv);
+  double* Uinv = reinterpret_cast<double*>(base + L.uinv);
+  double* R = reinterpret_cast<double*>(base + L.r);
+  double* T = reinterpret_cast<double*>(base + L.t);
+  double* V = reinterpret_cast<double*>(base + L.v);
+  double* H = reinterpret_cast<double*>(base + L.h);
+  double* cs = reinterpret_cast<double*>(base + L.cs);
+  double* sn = reinterpret_cast<double*>(base + L.sn);
+  double* g = reinterpret_cast<double*>(base + L.g);
+  double* y = reinterpret_cast<double*>(base + L.y);
+  double* h1 = reinterpret_cast<double*>(base + L.dots);
+  double* h2 = h1 + (m + 2);
+  double* ww = h2 + (m + 2);
+  GmresState* st = reinterpret_cast<GmresState*>(base + L.state);
+  if (zero_bytes(s, st, sizeof(GmresState)) != hipSuccess) return MLU_ERR_HIP;
+
+  const unsigned g2 = grid_for((size_t)n * n), g1 = grid_for((size_t)n), gw = (unsigned)((n + 3) / 4);
+  // LU := A, factored with the low-precision trailing products; the inverses
+  // of its 256 x 256 diagonal blocks; the norms of A and b; x := M^-1 b
+  hipLaunchKernelGGL(k_ir_copy, dim3(g2), dim3(256), 0, s, n, n, dA, lda, LU, n, nullptr);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, precision, nullptr, 0, -1,
+                             d_work, work_bytes, 0);
+  if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
+  const unsigned gi = grid_for((size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock);
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Linv);
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Uinv);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, true, true, n, LU, n, Linv) != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, false, false, n, LU, n, Uinv) != hipSuccess) return MLU_ERR_HIP;
+  hipLaunchKernelGGL(k_ir_anorm, dim3(gw), dim3(256), 0, s, n, dA, lda, &st->anorm);
+  hipLaunchKernelGGL(k_ir_colmax, dim3(g1), dim3(256), 0, s, n, 1, db, 1, &st->bnorm, nullptr);
+  hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, db, 1, dx, 1, nullptr);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+  if (getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, dx, 1, T, nullptr) != hipSuccess) return MLU_ERR_HIP;
+
+  const auto precondition = [&](double* v) {   // v := M^-1 v
+    return getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, v, 1, T, nullptr);
+  };
+  const unsigned gc = (unsigned)((n + 255) / 256);
+  bool gmres_mode = solver == MLU_IR_GMRES;
+  double prev_berr = 0.0;
+  int inner = 0;
+  GmresState hs{};
+  for (int it = 0;; ++it) {
+    // r := b - A x and the backward error of x
+    if (gemv(s, n, n, 1, dA, lda, dx, 1, db, 1, R, 1, nullptr) != hipSuccess) return MLU_ERR_HIP;
+    hipLaunchKernelGGL(k_ir_colmax, dim3(g1), dim3(256), 0, s, n, 1, R, 1, &st->rnorm, nullptr);
+    hipLaunchKernelGGL(k_ir_colmax, dim3(g1), dim3(256), 0, s, n, 1, dx, 1, &st->xnorm, nullptr);
+    hipLaunchKernelGGL(k_gmres_berr, dim3(1), dim3(64), 0, s, st);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    if (read_state(s, st, &hs) != hipSuccess) return MLU_ERR_HIP;
+    *h_berr = hs.berr;
+    *h_inner = inner;
+    if (hs.berr <= tol) {
+      *h_outer = it;
+      return 0;
+    }
+    if (it >= max_outer) {
+      *h_outer = -1;
+      return 0;
+    }
+    if (solver == MLU_IR_AUTO && !gmres_mode && it > 0 && !(hs.berr <= 0.5 * prev_berr)) gmres_mode = true;
+    prev_berr = hs.berr;
+    // z := M^-1 r, into the first basis vector
+    hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, R, 1, V, 1, nullptr);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    if (precondition(V) != hipSuccess) return MLU_ERR_HIP;
+    if (!gmres_mode) {   // LU-IR: x := x + z
+      hipLaunchKernelGGL(k_ir_axpy, dim3(g1), dim3(256), 0, s, n, 1, V, 1, dx, 1, nullptr);
+      if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+      continue;
+    }
+    // GMRES on M^-1 A d = z from d = 0
+    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, V, V, ww);
+    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(64), 0, s, st, ww, g, m);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    if (read_state(s, st, &hs) != hipSuccess) return MLU_ERR_HIP;
+    if (!(hs.beta > 0.0)) continue;   // z = 0 (or not finite): no correction to make
+    const double beta = hs.beta;
+    hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, V, &st->beta);
+    int steps = 0;
+    for (int k = 0; k < m; ++k) {
+      double* w = V + (size_t)(k + 1) * n;   // the next basis vector, built in place
+      if (gemv(s, n, n, 1, dA, lda, V + (size_t)k * n, 1, nullptr, 0, w, 1, nullptr) != hipSuccess)
+        return MLU_ERR_HIP;
+      if (precondition(w) != hipSuccess) return MLU_ERR_HIP;
+      hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h1);
+      hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h1, -1.0, w);
+      hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h2);
+      hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h2, -1.0, w);
+      hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, w, w, ww);
+      hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, st, k, m, h1, h2, ww, H, cs, sn, g);
+      if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+      if (read_state(s, st, &hs) != hipSuccess) return MLU_ERR_HIP;
+      steps = k + 1;
+      if (hs.resid <= gmres_tol * beta || !(hs.hnext > 0.0)) break;
+      hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, w, &st->hnext);
+    }
+    // d = V y, x := x + d
+    hipLaunchKernelGGL(k_hess_solve, dim3(1), dim3(64), 0, s, steps, m, H, g, y);
+    hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, steps, V, y, 1.0, dx);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    inner += steps;
+  }
 }
 
 }  // extern "C"

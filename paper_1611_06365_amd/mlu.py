@@ -21,6 +21,9 @@ MLU_INFO_BAD_PIVOT = -998
 MLU_MAX_NB_INNER = 16
 MLU_PREC_FP64, MLU_PREC_FP32, MLU_PREC_BF16 = 0, 1, 2
 PRECISION_IDS = {"fp64": MLU_PREC_FP64, "fp32": MLU_PREC_FP32, "bf16": MLU_PREC_BF16}
+MLU_IR_LU, MLU_IR_GMRES, MLU_IR_AUTO = 0, 1, 2
+IR_SOLVER_IDS = {"lu": MLU_IR_LU, "gmres": MLU_IR_GMRES, "auto": MLU_IR_AUTO}
+MLU_GMRES_MAX_KRYLOV = 512
 
 _vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
 
@@ -34,6 +37,9 @@ _SIGNATURES = {
     "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
                        _vp, _vp, _sz], _i),
+    "mlu_dsgesv_gmres_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
+    "mlu_dsgesv_gmres_ir": ([_vp, _i, _vp, _i, _vp, _vp, _i, _i, ctypes.c_double, _i, _i, ctypes.c_double, _i, _i,
+                             _i, _vp, _vp, _vp, _vp, _vp, _vp, _sz], _i),
     "mlu_getrf_batched_workspace": ([_i, ctypes.POINTER(_sz)], _i),
     "mlu_dgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _sz], _i),
     "mlu_sgetrf_batched": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _i, _i, _vp, _sz], _i),
@@ -107,6 +113,18 @@ def mlu_dsgesv_ir(stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, ma
                   d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes) -> int:
     return _call("mlu_dsgesv_ir", stream, n, nrhs, dA, lda, dB, ldb, dX, ldx, precision, tol, max_iter, variant, nb,
                  nb_inner, d_ipiv, d_info, d_iters, d_berr, d_work, work_bytes)
+
+
+def mlu_dsgesv_gmres_ir_workspace(n, max_krylov) -> tuple[int, int]:
+    out = _sz(0)
+    rc = _call("mlu_dsgesv_gmres_ir_workspace", n, max_krylov, ctypes.byref(out))
+    return rc, out.value
+
+
+def mlu_dsgesv_gmres_ir(stream, n, dA, lda, db, dx, precision, solver, tol, max_outer, max_krylov, gmres_tol,
+                        variant, nb, nb_inner, d_ipiv, d_info, h_outer, h_inner, h_berr, d_work, work_bytes) -> int:
+    return _call("mlu_dsgesv_gmres_ir", stream, n, dA, lda, db, dx, precision, solver, tol, max_outer, max_krylov,
+                 gmres_tol, variant, nb, nb_inner, d_ipiv, d_info, h_outer, h_inner, h_berr, d_work, work_bytes)
 
 
 def mlu_getrf_batched_workspace(batch) -> tuple[int, int]:
@@ -326,6 +344,42 @@ def gesv_ir(A, B, precision="fp32", tol=1e-13, max_iter=10, variant="la", nb=256
                        berr.data_ptr(), work.data_ptr(), work.numel())
     check(rc, "mlu_dsgesv_ir")
     return X, ipiv, info, iters, berr
+
+
+def gesv_gmres_ir(A, b, precision="fp32", solver="gmres", tol=1e-13, max_outer=10, max_krylov=64,
+                  gmres_tol=1e-6, variant="la", nb=256, nb_inner=0, x=None, work=None, stream=None):
+    """Solve A x = b by mixed-precision LU and FP64 refinement with GMRES
+    corrections (mlu_dsgesv_gmres_ir).  b is a length-n FP64 vector.
+
+    Returns (x, ipiv, info, outer, inner, berr): outer, inner and berr are host
+    values (the call waits for the stream); ipiv and info are device tensors.
+    A and b are not modified.
+    """
+    import torch
+
+    pa, lda = _rowmajor(A, "A")
+    n = A.shape[0]
+    if A.shape[1] != n or b.dim() != 1 or b.shape[0] != n:
+        raise ValueError("A must be n x n and b of length n")
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.device != A.device:
+        raise ValueError("b must be a contiguous float64 vector on A's device")
+    x = torch.empty_like(b) if x is None else x
+    if x.dtype != torch.float64 or not x.is_contiguous() or x.shape != b.shape or x.device != A.device:
+        raise ValueError("x must be a contiguous float64 vector like b")
+    if work is None:
+        rc, nbytes = mlu_dsgesv_gmres_ir_workspace(n, max_krylov)
+        check(rc, "mlu_dsgesv_gmres_ir_workspace")
+        work = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    info = torch.empty(1, dtype=torch.int32, device=A.device)
+    outer, inner, berr = _i(0), _i(0), ctypes.c_double(0.0)
+    v = VARIANT_IDS[variant] if isinstance(variant, str) else int(variant)
+    rc = mlu_dsgesv_gmres_ir(_stream(stream), n, pa, lda, b.data_ptr(), x.data_ptr(), PRECISION_IDS[precision],
+                             IR_SOLVER_IDS[solver], tol, max_outer, max_krylov, gmres_tol, v, nb, nb_inner,
+                             ipiv.data_ptr(), info.data_ptr(), ctypes.addressof(outer), ctypes.addressof(inner),
+                             ctypes.addressof(berr), work.data_ptr(), work.numel())
+    check(rc, "mlu_dsgesv_gmres_ir")
+    return x, ipiv, info, outer.value, inner.value, berr.value
 
 
 def trsm(T, B, uplo="L", diag="U", stream=None):

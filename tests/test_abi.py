@@ -155,3 +155,29 @@ def test_et_argument_checks(lib):
         kw = dict(base)
         kw[key] = bad
         assert mlu.mlu_dgetrf_et(*kw.values()) == code, key
+
+
+def test_gmres_ir_argument_checks(lib):
+    out = ctypes.c_size_t(0)
+    assert mlu.mlu_dsgesv_gmres_ir_workspace(-1, 8)[0] == -1
+    assert mlu.mlu_dsgesv_gmres_ir_workspace(4, 0)[0] == -2
+    assert mlu.mlu_dsgesv_gmres_ir_workspace(4, mlu.MLU_GMRES_MAX_KRYLOV + 1)[0] == -2
+    assert lib.mlu_dsgesv_gmres_ir_workspace(4, 8, None) == -3
+    rc, small = mlu.mlu_dsgesv_gmres_ir_workspace(100, 8)
+    rc2, big = mlu.mlu_dsgesv_gmres_ir_workspace(100, 64)
+    assert rc == rc2 == 0 and big > small >= 100 * 100 * 8 + 9 * 100 * 8
+    o, i, b = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    addr = lambda v: ctypes.addressof(v)  # noqa: E731
+    base = dict(stream=None, n=4, dA=8, lda=4, db=8, dx=8, precision=1, solver=1, tol=1e-13, max_outer=3,
+                max_krylov=8, gmres_tol=1e-6, variant=2, nb=2, nb_inner=0, d_ipiv=8, d_info=8, h_outer=addr(o),
+                h_inner=addr(i), h_berr=addr(b), d_work=8, work_bytes=1 << 40)
+    for key, bad, code in [("n", -1, -2), ("n", 40000, -2), ("dA", None, -3), ("lda", 3, -4), ("db", None, -5),
+                           ("dx", None, -6), ("precision", 3, -7), ("solver", 3, -8), ("tol", -1.0, -9),
+                           ("tol", float("nan"), -9), ("max_outer", -1, -10), ("max_krylov", 0, -11),
+                           ("max_krylov", mlu.MLU_GMRES_MAX_KRYLOV + 1, -11), ("gmres_tol", -1.0, -12),
+                           ("variant", 3, -13), ("nb", 0, -14), ("nb_inner", 17, -15), ("d_ipiv", None, -16),
+                           ("d_info", None, -17), ("h_outer", None, -18), ("h_inner", None, -19),
+                           ("h_berr", None, -20), ("d_work", None, -21), ("work_bytes", 16, -22)]:
+        kw = dict(base)
+        kw[key] = bad
+        assert mlu.mlu_dsgesv_gmres_ir(*kw.values()) == code, key

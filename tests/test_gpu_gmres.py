@@ -1,0 +1,172 @@
+"""GPU parity of mixed-precision LU with GMRES-IR (mlu_dsgesv_gmres_ir): the
+factorization's trailing products in FP32 or BF16, FP64 residuals, corrections
+from GMRES on the LU-preconditioned system (Carson and Higham).
+
+What is unique is the solution of A x = b, so the bars are against the FP64
+oracle (oracle LU + triangular solves):
+  * backward error <= 1e-13, on the device and recomputed on the host in FP64
+    by the oracle's definition (<= 2e-13: the host sums in another order);
+  * |x - x_64|_inf / |x_64|_inf <= 2 kappa_inf(A) (eta + eta_64), the
+    first-order perturbation bound for two solutions of A x = b with normwise
+    backward errors eta (this one, host) and eta_64 (the FP64 oracle's), with
+    kappa_inf = ||A||_inf ||A^-1||_inf computed on the host;
+  * info == 0; A and b unchanged.
+Iteration counts depend on rounding and are only checked for sanity, except
+where the method fixes them (MLU_IR_LU is mlu_dsgesv_ir step for step; exact
+FP64 factors need at most one correction; a met tolerance needs none).
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs as G
+import oracle as O
+from oracle.refine import backward_error
+from paper_1611_06365_amd import mlu
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mlu.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+_x64 = {}
+
+
+def oracle_solution(key, A, b):
+    """(x_64, its backward error, kappa_inf(A))."""
+    if key not in _x64:
+        F = A.copy()
+        piv, info = O.getrf(F, "rl", nb=64)
+        assert info == 0
+        x64 = O.getrs(F, piv, b.reshape(-1, 1))[:, 0]
+        kinf = np.abs(A).sum(axis=1).max() * np.abs(np.linalg.inv(A)).sum(axis=1).max()
+        _x64[key] = (x64, backward_error(A, x64, b), kinf)
+    return _x64[key]
+
+
+def solve(A, b, **kw):
+    dA, db = dev(A), dev(b)
+    x, ipiv, info, outer, inner, berr = mlu.gesv_gmres_ir(dA, db, **kw)
+    xh = host(x)
+    assert np.array_equal(host(dA), A) and np.array_equal(host(db), b), "A and b must not change"
+    return xh, int(host(info)[0]), outer, inner, berr
+
+
+@pytest.mark.parametrize("n,cond,precision,solver,variant,nb", [
+    (300, 1e2, "fp32", "gmres", "la", 64),
+    (300, 1e8, "fp32", "gmres", "la", 64),
+    (700, 1e8, "fp32", "gmres", "rl", 128),
+    (700, 1e8, "fp32", "auto", "la", 128),
+    (520, 1e5, "bf16", "gmres", "la", 64),
+    (300, 1e8, "bf16", "gmres", "la", 64),
+    (1100, 1e8, "fp32", "gmres", "la", 256),
+])
+def test_gmres_ir_reaches_fp64_backward_error(n, cond, precision, solver, variant, nb):
+    A = G.haar_spectrum(n, cond, seed=7)
+    b = G.gaussian_rhs(n, 1, seed=1)[:, 0]
+    x, info, outer, inner, be = solve(A, b, precision=precision, solver=solver, tol=1e-13, max_outer=10,
+                                      max_krylov=min(n, 300), gmres_tol=1e-6, variant=variant, nb=nb)
+    hb = backward_error(A, x, b)
+    x64, hb64, kinf = oracle_solution((n, cond), A, b)
+    fwd = np.abs(x - x64).max() / np.abs(x64).max()
+    bound = 2.0 * kinf * (hb + hb64)
+    print(f"gmres-ir {precision} {solver} n={n} cond={cond:g}: outer {outer}, inner {inner}, berr {be:.2e} "
+          f"(host {hb:.2e}), |x - x64|/|x64| {fwd:.2e} (bound {bound:.1e})", flush=True)
+    assert info == 0
+    assert 0 <= outer <= 10 and inner >= (1 if solver == "gmres" and outer > 0 else 0)
+    assert be <= 1e-13 and hb <= 2e-13
+    assert fwd <= bound
+
+
+def test_lu_ir_stalls_where_gmres_ir_converges():
+    n, cond = 600, 1e8
+    A = G.haar_spectrum(n, cond, seed=3)
+    b = G.gaussian_rhs(n, 1, seed=2)[:, 0]
+    _, _, outer_lu, inner_lu, be_lu = solve(A, b, precision="fp32", solver="lu", tol=1e-13, max_outer=8, nb=64)
+    _, _, outer_g, inner_g, be_g = solve(A, b, precision="fp32", solver="gmres", tol=1e-13, max_outer=8, nb=64)
+    _, _, outer_a, inner_a, be_a = solve(A, b, precision="fp32", solver="auto", tol=1e-13, max_outer=8, nb=64)
+    print(f"cond 1e8 fp32: lu {outer_lu} ({be_lu:.2e}), gmres {outer_g}/{inner_g} ({be_g:.2e}), "
+          f"auto {outer_a}/{inner_a} ({be_a:.2e})", flush=True)
+    assert outer_lu == -1 and be_lu > 1e-13 and inner_lu == 0
+    assert outer_g >= 1 and be_g <= 1e-13
+    assert outer_a >= 1 and inner_a >= 1 and be_a <= 1e-13
+
+
+def test_auto_stays_lu_ir_when_it_converges():
+    A = G.haar_spectrum(400, 1e2, seed=4)
+    b = G.gaussian_rhs(400, 1, seed=5)[:, 0]
+    x, info, outer, inner, be = solve(A, b, precision="fp32", solver="auto", tol=1e-13, nb=64)
+    assert info == 0 and 0 <= outer <= 3 and inner == 0 and be <= 1e-13
+
+
+def test_lu_mode_is_dsgesv_ir():
+    n = 450
+    A = G.haar_spectrum(n, 1e4, seed=6)
+    b = G.gaussian_rhs(n, 1, seed=6)
+    x, info, outer, inner, be = solve(A, b[:, 0], precision="fp32", solver="lu", tol=1e-14, max_outer=6, nb=64)
+    X, ipiv, info2, iters, berr = mlu.gesv_ir(dev(A), dev(b), precision="fp32", tol=1e-14, max_iter=6, nb=64)
+    assert info == int(host(info2)[0]) == 0
+    assert outer == int(host(iters)[0]) and inner == 0
+    assert be == float(host(berr)[0])
+    assert np.array_equal(x, host(X)[:, 0])
+
+
+def test_fp64_factors_need_at_most_one_correction():
+    A = G.haar_spectrum(350, 1e6, seed=8)
+    b = G.gaussian_rhs(350, 1, seed=8)[:, 0]
+    for solver in ("lu", "gmres"):
+        x, info, outer, inner, be = solve(A, b, precision="fp64", solver=solver, tol=1e-14, nb=64)
+        assert info == 0 and outer in (0, 1) and be <= 1e-14
+
+
+def test_repeated_calls_are_bitwise_identical():
+    A = G.haar_spectrum(500, 1e8, seed=9)
+    b = G.gaussian_rhs(500, 1, seed=9)[:, 0]
+    r1 = solve(A, b, precision="fp32", solver="gmres", nb=128)
+    r2 = solve(A, b, precision="fp32", solver="gmres", nb=128)
+    assert np.array_equal(r1[0], r2[0]) and r1[1:] == r2[1:]
+
+
+def test_edges_empty_tiny_met_tolerance_and_no_iterations():
+    e = torch.empty(0, 0, dtype=torch.float64, device=DEV)
+    x, ipiv, info, outer, inner, be = mlu.gesv_gmres_ir(e, torch.empty(0, dtype=torch.float64, device=DEV))
+    assert x.shape == (0,) and int(host(info)[0]) == 0 and outer == 0 and inner == 0 and be == 0.0
+    A = np.array([[4.0]])
+    x, info, outer, inner, be = solve(A, np.array([2.0]), precision="fp32", max_krylov=1)
+    assert info == 0 and outer == 0 and x[0] == 0.5 and be == 0.0
+    A = G.haar_spectrum(17, 1e3, seed=1)
+    b = G.gaussian_rhs(17, 1, seed=1)[:, 0]
+    x, info, outer, inner, be = solve(A, b, precision="bf16", solver="gmres", max_krylov=17, nb=8)
+    assert info == 0 and outer >= 0 and be <= 1e-13 and backward_error(A, x, b) <= 2e-13
+    # a tolerance the first solve already meets: no correction, no GMRES step
+    x, info, outer, inner, be = solve(A, b, precision="fp32", tol=1.0, nb=8)
+    assert outer == 0 and inner == 0 and be <= 1.0
+    # no corrections allowed and a tolerance out of reach: reported as not reached
+    x, info, outer, inner, be = solve(A, b, precision="bf16", tol=0.0, max_outer=0, nb=8)
+    assert outer == -1 and inner == 0 and be > 0.0
+    # one Krylov step per correction still converges on a well-conditioned matrix
+    x, info, outer, inner, be = solve(A, b, precision="fp32", solver="gmres", max_krylov=1, max_outer=20, nb=8)
+    assert outer >= 1 and inner == outer and be <= 1e-13
+
+
+def test_singular_factor_reports_info():
+    A = G.zero_column(64, seed=2, col=10)
+    b = G.gaussian_rhs(64, 1, seed=3)[:, 0]
+    x, info, outer, inner, be = solve(A, b, precision="fp32", solver="gmres", max_outer=2, nb=16)
+    assert info == 11
