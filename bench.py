@@ -324,6 +324,11 @@ def mixed_section(args, dev):
     work_ir = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     x64 = torch.empty((n, 1), dtype=torch.float64, device=dev)
     xmp = torch.empty((n, 1), dtype=torch.float64, device=dev)
+    rc, gbytes = mlu.mlu_dsgesv_gmres_ir_workspace(n, args.max_krylov)
+    mlu.check(rc, "mlu_dsgesv_gmres_ir_workspace")
+    work_g = torch.empty(gbytes, dtype=torch.uint8, device=dev)
+    b1 = b.view(n)
+    xg = torch.empty(n, dtype=torch.float64, device=dev)
 
     def timed(fn, reps=2):
         best = None
@@ -356,6 +361,8 @@ def mixed_section(args, dev):
         fp64()   # warm-up
         t64 = timed(fp64)
         for low, max_iter in (("fp32", 10), ("bf16", 30)):
+            if low not in args.mixed_precisions.split(","):
+                continue
             def mixedrun():
                 out["r"] = mlu.gesv_ir(A, b, precision=low, tol=1e-13, max_iter=max_iter, variant=args.variant,
                                        nb=args.nb, nb_inner=args.nb_inner, X=xmp, work=work_ir)
@@ -369,12 +376,30 @@ def mixed_section(args, dev):
                     "berr_fp64_recomputed": berr_of(A, x64), "berr_recomputed": berr_of(A, xmp),
                     "info": int(minfo.item()),
                     "rel_diff_vs_fp64_solve": float((xmp - x64).abs().max() / x64.abs().max())}
+            # LU-IR with the GMRES-IR fallback (mlu_dsgesv_gmres_ir, auto): the plain
+            # corrections while they at least halve berr, GMRES corrections after
+            out["g"] = None
+
+            def gmresrun():
+                out["g"] = mlu.gesv_gmres_ir(A, b1, precision=low, solver="auto", tol=1e-13, max_outer=10,
+                                             max_krylov=args.max_krylov, gmres_tol=1e-6, variant=args.variant,
+                                             nb=args.nb, nb_inner=args.nb_inner, x=xg, work=work_g)
+
+            tg = timed(gmresrun, reps=1)
+            _, _, ginfo, gouter, ginner, gberr = out["g"]
+            case["gmres_ir_auto"] = {"ms": round(tg, 3), "speedup": round(t64 / tg, 3), "outer": gouter,
+                                     "inner": ginner, "berr": gberr, "berr_recomputed": berr_of(A, xg.view(n, 1)),
+                                     "info": int(ginfo.item()),
+                                     "rel_diff_vs_fp64_solve": float((xg.view(n, 1) - x64).abs().max()
+                                                                     / x64.abs().max())}
             log(f"mixed cond={cond:g} {low}: {case}")
             cases.append(case)
         del A
     return {"what": "FP32- and BF16-product trailing updates (FP32 accumulation; FP64 panel, solves, residual, "
                     "correction) + FP64 iterative refinement to backward error <= 1e-13, vs the FP64 solve "
-                    "(getrf + getrs + residual)",
+                    "(getrf + getrs + residual); per case LU-IR (mlu_dsgesv_ir) and LU-IR with the GMRES-IR "
+                    "fallback (mlu_dsgesv_gmres_ir, auto: GMRES corrections once a plain one fails to halve berr; "
+                    f"GMRES tolerance 1e-6, Krylov limit {args.max_krylov}, at most 10 corrections)",
             "n": n, "nrhs": 1, "matrix": "Q diag(logspace(0,-log10 cond,n)) Q^T, Q Haar (seed 0), b ~ N(0,1)",
             "cases": cases}
 
@@ -394,6 +419,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision + refinement measurement")
     ap.add_argument("--mixed-conds", default="1e2,1e5,1e8")
+    ap.add_argument("--mixed-precisions", default="fp32,bf16", help="product precisions of the mixed rows")
+    ap.add_argument("--max-krylov", type=int, default=200, help="GMRES-IR Krylov dimension limit")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
     ap.add_argument("--no-et", action="store_true", help="skip the early-termination comparison")
     ap.add_argument("--grid", action="store_true",
