@@ -113,7 +113,8 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int k0) {
+    (void)k0;
     double* pa = &As[buf][ar * LDS_A + ac];
     double* pb = &Bs[buf][br * LDS_B + bc];
 #pragma unroll
@@ -149,7 +150,7 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
 
   for (int kt = 0; kt < nk; ++kt) {
@@ -175,7 +176,7 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st & 1][i], b[st & 1][j], acc[i][j], 0, 0, 0);
     }
 
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
@@ -208,6 +209,35 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
 // layout of the 16 x 16 f32 block (measured on gfx950): lane (li, lq) holds
 // rows 4 lq + r (r = 0..3) of column li.
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// C -= acc for a 128 x 128 tile whose FP32 accumulators hold, in each 16 x 16
+// block, rows rb + 16 i + r (r = 0..3) of column cb + 16 j: the C values of
+// two 16-row blocks at a time (32 per lane) are loaded, from addresses clamped
+// into C, before the first is used, so those loads are in flight together;
+// out-of-range elements are not stored.
+__device__ __forceinline__ void sub_acc_f32(const v4f (&acc)[4][4], double* __restrict__ C, int ldc, int m, int n,
+                                            int rb, int cb) {
+#pragma unroll
+  for (int i0 = 0; i0 < 4; i0 += 2) {
+    double cv[2][4][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          cv[i][j][r] = C[(size_t)min(rb + (i0 + i) * 16 + r, m - 1) * ldc + min(cb + j * 16, n - 1)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rb + (i0 + i) * 16 + r, col = cb + j * 16;
+          if (row < m && col < n) C[(size_t)row * ldc + col] = cv[i][j][r] - (double)acc[i0 + i][j][r];
+        }
+  }
+}
 constexpr int LDSF_A = BK + 4;   // floats per A row in LDS
 constexpr int LDSF_B = BN + 4;
 
@@ -241,22 +271,26 @@ __device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int 
         rb[2 * e] = y.x;
         rb[2 * e + 1] = y.y;
       }
-    } else {
-      const int gr = row0 + ar;
+    } else {   // unconditional loads from clamped addresses; sstore masks the inner dimension
+      const int gr = min(row0 + ar, m - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = A[(size_t)gr * lda + min(k0 + ac + e, k - 1)];
+      const int gk = min(k0 + br, k - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = B[(size_t)gk * ldb + min(col0 + bc + e, n - 1)];
+    }
+  };
+  auto kmask = [&](int k0) {
+    if (!(VEC && interior_mn && k0 + BK <= k)) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + ac + e;
-        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
-      }
-      const int gk = k0 + br;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gc = col0 + bc + e;
-        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+        if (k0 + ac + e >= k) ra[e] = 0.0;
+        if (k0 + br >= k) rb[e] = 0.0;
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int k0) {
+    kmask(k0);
     float* pa = &Asf[buf][ar * LDSF_A + ac];
     float* pb = &Bsf[buf][br * LDSF_B + bc];
 #pragma unroll
@@ -276,7 +310,7 @@ __device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int 
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -300,24 +334,11 @@ __device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int 
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][st], b[j][st], acc[i][j], 0, 0, 0);
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
-  double* const cbase = C + (size_t)(row0 + wm * 64 + 4 * lq) * ldc + col0 + wn * 64 + li;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 64 + i * 16 + 4 * lq + r;
-        const int col = col0 + wn * 64 + j * 16 + li;
-        if (interior_mn || (row < m && col < n)) {
-          double* pc = cbase + (size_t)(i * 16 + r) * ldc + j * 16;
-          *pc = *pc - (double)acc[i][j][r];
-        }
-      }
+  sub_acc_f32(acc, C, ldc, m, n, row0 + wm * 64 + 4 * lq, col0 + wn * 64 + li);
 }
 
 // A 64 x 64 tile of C := C - A B in FP64, for launches with too few 128 x 128
@@ -359,22 +380,23 @@ __device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, in
         rb[2 * e] = -y.x;
         rb[2 * e + 1] = -y.y;
       }
-    } else {
-      const int gr = row0 + ar;
+    } else {   // unconditional loads from clamped addresses; sstore masks the inner dimension
+      const int gr = min(row0 + ar, m - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gk = k0 + ac + e;
-        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
-      }
-      const int gk = k0 + br;
+      for (int e = 0; e < 4; ++e) ra[e] = A[(size_t)gr * lda + min(k0 + ac + e, k - 1)];
+      const int gk = min(k0 + br, k - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gc = col0 + bc + e;
-        rb[e] = (gk < k && gc < n) ? -B[(size_t)gk * ldb + gc] : 0.0;
-      }
+      for (int e = 0; e < 4; ++e) rb[e] = -B[(size_t)gk * ldb + min(col0 + bc + e, n - 1)];
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int k0) {
+    if (!(VEC && interior_mn && k0 + BK <= k)) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (k0 + ac + e >= k) ra[e] = 0.0;
+        if (k0 + br >= k) rb[e] = 0.0;
+      }
+    }
     double* pa = &As[buf][ar * LDS_A + ac];
     double* pb = &Bs[buf][br * LDS_SB + bc];
 #pragma unroll
@@ -392,15 +414,15 @@ __device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, in
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 32 + i * 16 + lq + 4 * r;
-        const int col = col0 + wn * 32 + j * 16 + li;
-        acc[i][j][r] = (interior_mn || (row < m && col < n)) ? cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16] : 0.0;
+      for (int r = 0; r < 4; ++r) {   // clamped: an accumulator outside C is never stored
+        const int row = min(row0 + wm * 32 + i * 16 + lq + 4 * r, m - 1);
+        const int col = min(col0 + wn * 32 + j * 16 + li, n - 1);
+        acc[i][j][r] = C[(size_t)row * ldc + col];
       }
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -418,7 +440,7 @@ __device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, in
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
@@ -481,22 +503,26 @@ __device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int
         rb[2 * e] = y.x;
         rb[2 * e + 1] = y.y;
       }
-    } else {
-      const int gr = row0 + ar;
+    } else {   // unconditional loads from clamped addresses; sstore masks the inner dimension
+      const int gr = min(row0 + ar, m - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = A[(size_t)gr * lda + min(k0 + ac + e, k - 1)];
+      const int gk = min(k0 + br, k - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = B[(size_t)gk * ldb + min(col0 + bc + e, n - 1)];
+    }
+  };
+  auto kmask = [&](int k0) {
+    if (!(VEC && interior_mn && k0 + BK <= k)) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + ac + e;
-        ra[e] = (gr < m && gk < k) ? A[(size_t)gr * lda + gk] : 0.0;
-      }
-      const int gk = k0 + br;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gc = col0 + bc + e;
-        rb[e] = (gk < k && gc < n) ? B[(size_t)gk * ldb + gc] : 0.0;
+        if (k0 + ac + e >= k) ra[e] = 0.0;
+        if (k0 + br >= k) rb[e] = 0.0;
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int k0) {
+    kmask(k0);
     unsigned short ha[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) ha[e] = to_bf16(ra[e]);
@@ -518,7 +544,7 @@ __device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int
 
   const int nk = (k + BK - 1) / BK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -533,24 +559,11 @@ __device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (kt + 1 < nk) sstore(buf ^ 1);
+    if (kt + 1 < nk) sstore(buf ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
-  double* const cbase = C + (size_t)(row0 + wm * 64 + 4 * lq) * ldc + col0 + wn * 64 + li;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 64 + i * 16 + 4 * lq + r;
-        const int col = col0 + wn * 64 + j * 16 + li;
-        if (interior_mn || (row < m && col < n)) {
-          double* pc = cbase + (size_t)(i * 16 + r) * ldc + j * 16;
-          *pc = *pc - (double)acc[i][j][r];
-        }
-      }
+  sub_acc_f32(acc, C, ldc, m, n, row0 + wm * 64 + 4 * lq, col0 + wn * 64 + li);
 }
 
 // one tile in the requested product precision

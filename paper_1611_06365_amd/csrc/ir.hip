@@ -85,12 +85,16 @@ __global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, cons
   if (row >= rows) return;
   const double* a = A + (size_t)row * lda;
   for (int c0 = 0; c0 < nrhs; c0 += 4) {
+    // right-hand sides past nrhs are read from the last one (clamped) and
+    // dropped at the store: unconditional loads stay in flight together
+    int cq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cq[q] = min(c0 + q, nrhs - 1);
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = lane; j < cols; j += 64) {
       const double aj = a[j];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (c0 + q < nrhs) s[q] += aj * X[(size_t)j * ldx + c0 + q];
+      for (int q = 0; q < 4; ++q) s[q] += aj * X[(size_t)j * ldx + cq[q]];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {

@@ -82,10 +82,20 @@ __global__ __launch_bounds__(kThreads) void k_laswp(double* __restrict__ A, int 
   const int col = g < na ? ca0 + g : cb0 + (g - na);
   const int e0 = tid / kCols, estep = kThreads / kCols;
 
-  for (int s = e0; s < 2 * nst; s += estep) {
-    const int src = s_label[s];
-    if (s_row[s] >= 0 && src != s && colok) s_buf[s][tid % kCols] = A[(size_t)s_row[src] * lda + col];
+  // every slot is read, from a clamped row and column (an unused slot's LDS
+  // entry is never written back), all of this thread's loads first, so they
+  // do not wait for one another
+  const int colc = colok ? col : (na > 0 ? ca0 : cb0);
+  constexpr int kPer = 2 * kMaxSteps / (kThreads / kCols);   // slots per thread, at most
+  double v[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    const int sl = min(e0 + t * estep, 2 * nst - 1);
+    v[t] = A[(size_t)max(s_row[s_label[sl]], 0) * lda + colc];
   }
+#pragma unroll
+  for (int t = 0; t < kPer; ++t)
+    if (e0 + t * estep < 2 * nst) s_buf[e0 + t * estep][tid % kCols] = v[t];
   __syncthreads();
   for (int s = e0; s < 2 * nst; s += estep) {
     const int src = s_label[s];

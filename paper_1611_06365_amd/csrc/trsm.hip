@@ -63,22 +63,26 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
     const int rlo = LOWER ? ib + kDiag : 0;
     const int rhi = LOWER ? nr : ib;
     const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
+    // This thread's entry of T's diagonal block is loaded first, so that
+    // waiting for it does not wait for the update's loads below.  All loads
+    // are unconditional, from addresses clamped into the triangle (rows < nr,
+    // columns ib..ib+bs-1), and masked where they are used: a select at issue
+    // would make every load wait for its own result.
+    const int dr = tid / kDiag, dc = tid % kDiag;
+    const double tdv = T[(size_t)(ib + min(dr, bs - 1)) * ldt + ib + min(dc, bs - 1)];
     double ta[kItems][4];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const int item = wave + 4 * i;
-      const int tr = rlo + (item >> 1) * 16 + li;
+      const int tr = min(rlo + (item >> 1) * 16 + li, nr - 1);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        const int k = 4 * lq + st;   // MFMA step st feeds lane group lq with k = 4 lq + st
-        ta[i][st] = (item < 2 * nrb && tr < nr && k < bs) ? -T[(size_t)tr * ldt + ib + k] : 0.0;
+        const int k = min(4 * lq + st, bs - 1);   // MFMA step st feeds lane group lq with k = 4 lq + st
+        ta[i][st] = T[(size_t)tr * ldt + ib + k];
       }
     }
     // T's diagonal block -> LDS
-    {
-      const int r = tid / kDiag, c = tid % kDiag;
-      Td[r][c] = (r < bs && c < bs) ? T[(size_t)(ib + r) * ldt + ib + c] : 0.0;
-    }
+    Td[dr][dc] = (dr < bs && dc < bs) ? tdv : 0.0;
     __syncthreads();
     // solve the block's rows, one column per thread
     if (tid < kCols) {
@@ -119,13 +123,15 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
       const int item = wave + 4 * i;
       if (item < 2 * nrb) {
         const int R0 = rlo + (item >> 1) * 16, ch = (item & 1) * 16;
+        const bool row_ok = R0 + li < nr;
         v4d acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] = X[(R0 + lq + 4 * r) * kPitch + ch + li];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const double b = X[(ib + 4 * lq + st) * kPitch + ch + li];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[i][st], b, acc, 0, 0, 0);
+          const double a = (row_ok && 4 * lq + st < bs) ? -ta[i][st] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) X[(R0 + lq + 4 * r) * kPitch + ch + li] = acc[r];
