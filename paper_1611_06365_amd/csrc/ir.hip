@@ -73,9 +73,10 @@ __global__ __launch_bounds__(256) void k_ir_colmax(int n, int nrhs, const double
 }
 
 // Out = Y - A X, or Out = A X when Y is null (FP64; A rows x cols, X cols x
-// nrhs): one wave per row of A, right-hand sides in groups of 4.  Out may be Y
+// nrhs): one wave per row of A, NQ right-hand sides at a time.  Out may be Y
 // (each element is read and written by the same lane).  Serves as the
 // residual (A n x n) and as the block steps of the triangular solves.
+template <int NQ>
 __global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, const double* __restrict__ A, int lda,
                                               const double* __restrict__ X, int ldx, const double* Y, int ldy,
                                               double* Out, int ldo, const int32_t* __restrict__ skip) {
@@ -84,20 +85,37 @@ __global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, cons
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
   const double* a = A + (size_t)row * lda;
-  for (int c0 = 0; c0 < nrhs; c0 += 4) {
+  for (int c0 = 0; c0 < nrhs; c0 += NQ) {
     // right-hand sides past nrhs are read from the last one (clamped) and
-    // dropped at the store: unconditional loads stay in flight together
-    int cq[4];
+    // dropped at the store: the loads are unconditional, four columns of A
+    // per lane at a time, so they stay in flight together
+    int cq[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cq[q] = min(c0 + q, nrhs - 1);
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = lane; j < cols; j += 64) {
+    for (int q = 0; q < NQ; ++q) cq[q] = min(c0 + q, nrhs - 1);
+    double s[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+    int j = lane;
+    for (; j + 192 < cols; j += 256) {
+      double av[4], xv[4][NQ];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = a[j + 64 * u];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) xv[u][q] = X[(size_t)(j + 64 * u) * ldx + cq[q]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q] += av[u] * xv[u][q];
+    }
+    for (; j < cols; j += 64) {
       const double aj = a[j];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s[q] += aj * X[(size_t)j * ldx + cq[q]];
+      for (int q = 0; q < NQ; ++q) s[q] += aj * X[(size_t)j * ldx + cq[q]];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const double t = wave_sum(s[q]);
       if (lane == 0 && c0 + q < nrhs) {
         const double y = Y != nullptr ? Y[(size_t)row * ldy + c0 + q] : 0.0;
@@ -110,9 +128,40 @@ __global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, cons
 hipError_t gemv(hipStream_t s, int rows, int cols, int nrhs, const double* A, int lda, const double* X, int ldx,
                 const double* Y, int ldy, double* Out, int ldo, const int32_t* skip) {
   if (rows <= 0 || nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemv, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, cols, nrhs, A, lda, X, ldx, Y,
-                     ldy, Out, ldo, skip);
+  const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_gemv<1>, grid, block, 0, s, rows, cols, nrhs, A, lda, X, ldx, Y, ldy, Out, ldo, skip);
+  else
+    hipLaunchKernelGGL(k_gemv<4>, grid, block, 0, s, rows, cols, nrhs, A, lda, X, ldx, Y, ldy, Out, ldo, skip);
   return hipGetLastError();
+}
+
+// perm := the row order of P from the sequential interchanges ipiv (1-based;
+// (P b)[i] = b[perm[i]]): one workgroup, the permutation composed in LDS by
+// one thread, n <= kPermMax (the callers' limit on n).
+constexpr int kPermMax = kPanelMaxRows;
+static_assert(kPermMax * sizeof(int32_t) <= 160 * 1024, "the permutation must fit in LDS");
+__global__ __launch_bounds__(256) void k_perm_from_ipiv(int n, const int32_t* __restrict__ ipiv,
+                                                        int32_t* __restrict__ perm) {
+  __shared__ int32_t p[kPermMax];
+  for (int i = threadIdx.x; i < n; i += 256) p[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < n; ++c) {
+      const int q = min(max(ipiv[c] - 1, c), n - 1);   // a legal interchange partner (c <= q < n)
+      const int t = p[c];
+      p[c] = p[q];
+      p[q] = t;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) perm[i] = p[i];
+}
+
+// Out[i] := X[perm[i]] (one right-hand side)
+__global__ void k_gather(int n, const int32_t* __restrict__ perm, const double* __restrict__ X,
+                         double* __restrict__ Out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) Out[i] = X[perm[i]];
 }
 
 // leading nr x nr of every 256 x 256 block := identity, the rest zero
@@ -128,19 +177,30 @@ __global__ void k_identity_blocks(int n, double* __restrict__ Inv) {
 // B := U^-1 L^-1 P B with the inverted diagonal blocks (Linv, Uinv): per
 // 256-row block a GEMV with the block's inverse, then a GEMV update of the
 // rows still to be solved.  tmp: n x nrhs (leading dimension nrhs).
+// perm / ybuf (optional, one right-hand side): P is applied by a gather of B
+// into ybuf through perm (k_perm_from_ipiv) instead of interchanges in place.
 hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int ld, const int32_t* ipiv,
                          const double* Linv, const double* Uinv, double* Bx, int ldb, double* tmp,
-                         const int32_t* skip) {
-  if (laswp(s, Bx, ldb, n, 0, n, ipiv, 0, nrhs, 0, 0, nullptr, skip) != hipSuccess) return hipErrorUnknown;
+                         const int32_t* skip, const int32_t* perm = nullptr, double* ybuf = nullptr) {
+  double* Y = Bx;
+  int ldy = ldb;
+  if (perm != nullptr && nrhs == 1) {
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)min((n + 255) / 256, 65536)), dim3(256), 0, s, n, perm, Bx, ybuf);
+    MLU_IR_TRY(hipGetLastError());
+    Y = ybuf;
+    ldy = 1;
+  } else if (laswp(s, Bx, ldb, n, 0, n, ipiv, 0, nrhs, 0, 0, nullptr, skip) != hipSuccess) {
+    return hipErrorUnknown;
+  }
   const int nblk = (n + kInvBlock - 1) / kInvBlock;
   const size_t bsz = (size_t)kInvBlock * kInvBlock;
-  for (int k = 0; k < nblk; ++k) {   // L: y := B (in place), x_k = Linv_k y_k -> tmp
+  for (int k = 0; k < nblk; ++k) {   // L: y := P B (in place), x_k = Linv_k y_k -> tmp
     const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
-    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Linv + k * bsz, kInvBlock, Bx + (size_t)r0 * ldb, ldb, nullptr, 0,
+    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Linv + k * bsz, kInvBlock, Y + (size_t)r0 * ldy, ldy, nullptr, 0,
                     tmp + (size_t)r0 * nrhs, nrhs, skip));
     if (r0 + nbk < n)
       MLU_IR_TRY(gemv(s, n - r0 - nbk, nbk, nrhs, LU + (size_t)(r0 + nbk) * ld + r0, ld, tmp + (size_t)r0 * nrhs,
-                      nrhs, Bx + (size_t)(r0 + nbk) * ldb, ldb, Bx + (size_t)(r0 + nbk) * ldb, ldb, skip));
+                      nrhs, Y + (size_t)(r0 + nbk) * ldy, ldy, Y + (size_t)(r0 + nbk) * ldy, ldy, skip));
   }
   for (int k = nblk - 1; k >= 0; --k) {   // U: z := tmp (in place), x_k = Uinv_k z_k -> B
     const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
@@ -329,7 +389,7 @@ __global__ void k_gmres_berr(GmresState* st) {
 }
 
 struct GmresLayout {
-  size_t lu, linv, uinv, r, t, v, h, cs, sn, g, y, dots, state, total;
+  size_t lu, linv, uinv, r, t, yb, perm, v, h, cs, sn, g, y, dots, state, total;
 };
 GmresLayout gmres_layout(int n, int m) {
   GmresLayout L;
@@ -340,7 +400,9 @@ GmresLayout gmres_layout(int n, int m) {
   L.uinv = align_up(L.linv + inv);
   L.r = align_up(L.uinv + inv);
   L.t = align_up(L.r + vec);
-  L.v = align_up(L.t + vec);
+  L.yb = align_up(L.t + vec);
+  L.perm = align_up(L.yb + vec);
+  L.v = align_up(L.perm + (size_t)n * sizeof(int32_t));
   L.h = align_up(L.v + (size_t)(m + 1) * vec);
   L.cs = align_up(L.h + (size_t)m * (m + 1) * sizeof(double));
   L.sn = align_up(L.cs + small);
@@ -512,6 +574,8 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   double* Uinv = reinterpret_cast<double*>(base + L.uinv);
   double* R = reinterpret_cast<double*>(base + L.r);
   double* T = reinterpret_cast<double*>(base + L.t);
+  double* Yb = reinterpret_cast<double*>(base + L.yb);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + L.perm);
   double* V = reinterpret_cast<double*>(base + L.v);
   double* H = reinterpret_cast<double*>(base + L.h);
   double* cs = reinterpret_cast<double*>(base + L.cs);
@@ -542,11 +606,13 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   hipLaunchKernelGGL(k_ir_colmax, dim3(g1), dim3(256), 0, s, n, 1, db, 1, &st->bnorm, nullptr);
   hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, db, 1, dx, 1, nullptr);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  if (getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, dx, 1, T, nullptr) != hipSuccess) return MLU_ERR_HIP;
-
+  hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(256), 0, s, n, d_ipiv, perm);
+  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   const auto precondition = [&](double* v) {   // v := M^-1 v
-    return getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, v, 1, T, nullptr);
+    return getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, v, 1, T, nullptr, perm, Yb);
   };
+  if (precondition(dx) != hipSuccess) return MLU_ERR_HIP;
+
   const unsigned gc = (unsigned)((n + 255) / 256);
   bool gmres_mode = solver == MLU_IR_GMRES;
   double prev_berr = 0.0;
