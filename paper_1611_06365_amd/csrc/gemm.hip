@@ -65,7 +65,13 @@ __device__ __forceinline__ unsigned hw_cu_id() { return (__builtin_amdgcn_s_getr
 
 // One 128 x 128 tile of C := C - A B.  Ends with a workgroup barrier, so the
 // caller may start another tile at once.
-template <bool VEC>
+// CLAMP selects the edge-tile form: unconditional loads from clamped addresses
+// (the inner dimension masked as the stage goes to LDS; a C element outside
+// the matrix is loaded from a clamped address and never stored), so edge
+// loads stay in flight together; without it, edge loads are conditional, which
+// keeps the persistent kernel's registers (it never sees edges at the sizes it
+// serves) as they are.
+template <bool VEC, bool CLAMP = false>
 __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
                                           int lda, const double* __restrict__ B, int ldb,
                                           double* __restrict__ C, int ldc) {
@@ -98,6 +104,13 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
         rb[2 * e] = -y.x;
         rb[2 * e + 1] = -y.y;
       }
+    } else if constexpr (CLAMP) {
+      const int gr = min(row0 + ar, m - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[e] = A[(size_t)gr * lda + min(k0 + ac + e, k - 1)];
+      const int gk = min(k0 + br, k - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[e] = -B[(size_t)gk * ldb + min(col0 + bc + e, n - 1)];
     } else {
       const int gr = row0 + ar;
 #pragma unroll
@@ -114,7 +127,15 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
     }
   };
   auto sstore = [&](int buf, int k0) {
-    (void)k0;
+    if constexpr (CLAMP) {
+      if (!(VEC && interior_mn && k0 + BK <= k)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (k0 + ac + e >= k) ra[e] = 0.0;
+          if (k0 + br >= k) rb[e] = 0.0;
+        }
+      }
+    }
     double* pa = &As[buf][ar * LDS_A + ac];
     double* pb = &Bs[buf][br * LDS_B + bc];
 #pragma unroll
@@ -135,6 +156,17 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[i][j][r] = cbase[(size_t)(i * 16 + 4 * r) * ldc + j * 16];
+  } else if constexpr (CLAMP) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(row0 + wm * 64 + i * 16 + lq + 4 * r, m - 1);
+          const int col = min(col0 + wn * 64 + j * 16 + li, n - 1);
+          acc[i][j][r] = C[(size_t)row * ldc + col];
+        }
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -567,13 +599,13 @@ __device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int
 }
 
 // one tile in the requested product precision
-template <bool VEC, int PREC>
+template <bool VEC, int PREC, bool CLAMP = false>
 __device__ __forceinline__ void tile_any(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
                                          int lda, const double* __restrict__ B, int ldb, double* __restrict__ C,
                                          int ldc) {
   if constexpr (PREC == kPrecF32) gemm_tile_f32<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
   else if constexpr (PREC == kPrecBF16) gemm_tile_bf16<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
-  else gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  else gemm_tile<VEC, CLAMP>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
 // Generic launches (inner panel updates, blocked triangular solves) and the
@@ -587,7 +619,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(int m, int n, int k, con
   if (skip != nullptr && *skip != 0) return;   // a flag the caller raised on the device
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  gemm_tile<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  gemm_tile<VEC, true>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 template <bool VEC, int PREC>
 __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, const double* __restrict__ A,
@@ -596,7 +628,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_trailing(int m, int n, int k, c
                                                           int tiles_n) {
   int tm, tn;
   tile_coords(blockIdx.x, tiles_m, tiles_n, tm, tn);
-  tile_any<VEC, PREC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+  tile_any<VEC, PREC, true>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
 // The 64 x 64 tile form of both (FP64 only), chosen by the host for launches

@@ -54,8 +54,17 @@ __global__ __launch_bounds__(256) void k_ir_anorm(int n, const double* __restric
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const double* a = A + (size_t)row * lda;
-  double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += fabs(a[j]);
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};   // four strided partial sums: four loads in flight
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[j + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4[u] += fabs(v[u]);
+  }
+  for (; j < n; j += 64) s4[0] += fabs(a[j]);
+  double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   s = wave_sum(s);
   if (lane == 0) atomicMax(out, dbits(s));
 }
@@ -301,8 +310,20 @@ __global__ __launch_bounds__(256) void k_dots(int n, int k, const double* __rest
   const int j = blockIdx.x;
   if (j >= k) return;
   const double* v = V + (size_t)j * n;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += v[i] * w[i];
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};   // four strided partial sums: four loads in flight
+  int i = threadIdx.x;
+  for (; i + 768 < n; i += 1024) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = v[i + 256 * u];
+      b[u] = w[i + 256 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4[u] += a[u] * b[u];
+  }
+  for (; i < n; i += 256) s4[0] += v[i] * w[i];
+  double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();

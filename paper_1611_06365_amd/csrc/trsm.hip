@@ -27,7 +27,7 @@ constexpr int kDiag = 16;      // diagonal block
 // own square B block at B + y b_stride (the inverses of the diagonal blocks
 // when B holds identities).
 template <bool LOWER, bool UNIT>
-__global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const double* __restrict__ T, int ldt,
+__global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const double* __restrict__ T, int ldt,
                                                   double* __restrict__ B, int ldb,
                                                   const int32_t* __restrict__ skip, int n_total,
                                                   long long b_stride) {
@@ -45,14 +45,34 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
   const int li = lane & 15, lq = lane >> 4;
   const int c0 = blockIdx.x * kCols;
 
-  // B block -> LDS (rows >= nr and columns >= ncols are zero and never stored)
-  for (int e = tid; e < kRows * kCols; e += 256) {
-    const int r = e / kCols, c = e % kCols;
-    X[r * kPitch + c] = (r < nr && c0 + c < ncols) ? B[(size_t)r * ldb + c0 + c] : 0.0;
+  // B block -> LDS (rows >= nr and columns >= ncols are zero and never
+  // stored): all of this thread's loads are issued first, unconditionally
+  // from clamped addresses, then masked into LDS
+  {
+    constexpr int kPer = kRows * kCols / 256;
+    double bv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + 256 * i, r = e / kCols, c = e % kCols;
+      bv[i] = B[(size_t)min(r, nr - 1) * ldb + min(c0 + c, ncols - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + 256 * i, r = e / kCols, c = e % kCols;
+      X[r * kPitch + c] = (r < nr && c0 + c < ncols) ? bv[i] : 0.0;
+    }
   }
 
   const int nblk = (nr + kDiag - 1) / kDiag;
   constexpr int kItems = 2 * (kRows / 16) / 4;   // update items per wave, at most
+  // this thread's entry of T's diagonal block, loaded one step ahead
+  const int dr = tid / kDiag, dc = tid % kDiag;
+  auto diag_entry = [&](int step) {
+    const int blk = LOWER ? step : nblk - 1 - step;
+    const int bsz = min(kDiag, nr - blk * kDiag);
+    return T[(size_t)(blk * kDiag + min(dr, bsz - 1)) * ldt + blk * kDiag + min(dc, bsz - 1)];
+  };
+  double tdv = diag_entry(0);
   for (int step = 0; step < nblk; ++step) {
     const int blk = LOWER ? step : nblk - 1 - step;
     const int ib = blk * kDiag;
@@ -63,13 +83,9 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
     const int rlo = LOWER ? ib + kDiag : 0;
     const int rhi = LOWER ? nr : ib;
     const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
-    // This thread's entry of T's diagonal block is loaded first, so that
-    // waiting for it does not wait for the update's loads below.  All loads
-    // are unconditional, from addresses clamped into the triangle (rows < nr,
-    // columns ib..ib+bs-1), and masked where they are used: a select at issue
-    // would make every load wait for its own result.
-    const int dr = tid / kDiag, dc = tid % kDiag;
-    const double tdv = T[(size_t)(ib + min(dr, bs - 1)) * ldt + ib + min(dc, bs - 1)];
+    // The loads are unconditional, from addresses clamped into the triangle
+    // (rows < nr, columns ib..ib+bs-1), and masked where they are used: a
+    // select at issue would make every load wait for its own result.
     double ta[kItems][4];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
@@ -81,41 +97,40 @@ __global__ __launch_bounds__(256) void k_trsm_lds(int nr, int ncols, const doubl
         ta[i][st] = T[(size_t)tr * ldt + ib + k];
       }
     }
-    // T's diagonal block -> LDS
+    // T's diagonal block -> LDS (zero outside the block), then the next
+    // step's entry is requested
     Td[dr][dc] = (dr < bs && dc < bs) ? tdv : 0.0;
+    if (step + 1 < nblk) tdv = diag_entry(step + 1);
     __syncthreads();
-    // solve the block's rows, one column per thread
+    // solve the block's rows, one column per thread.  No branch on the block
+    // size: rows past bs are rows past nr, zero in LDS, and T is zero there,
+    // so they only ever subtract exact zeros (and are divided only when
+    // r < bs).  Lower: column by column, each row receives its terms in the
+    // order of substitution (q ascending), so the result is the row-by-row
+    // one, while the rows of one column update independently.
     if (tid < kCols) {
       double x[kDiag];
 #pragma unroll
       for (int r = 0; r < kDiag; ++r) x[r] = X[(ib + r) * kPitch + tid];
       if (LOWER) {
 #pragma unroll
-        for (int r = 0; r < kDiag; ++r) {
-          if (r < bs) {
-            double v = x[r];
+        for (int q = 0; q < kDiag; ++q) {
+          if (!UNIT) x[q] = q < bs ? x[q] / Td[q][q] : x[q];
 #pragma unroll
-            for (int q = 0; q < r; ++q) v = v - Td[r][q] * x[q];
-            if (!UNIT) v = v / Td[r][r];
-            x[r] = v;
-          }
+          for (int r = q + 1; r < kDiag; ++r) x[r] = x[r] - Td[r][q] * x[q];
         }
       } else {
 #pragma unroll
         for (int r = kDiag - 1; r >= 0; --r) {
-          if (r < bs) {
-            double v = x[r];
+          double v = x[r];
 #pragma unroll
-            for (int q = r + 1; q < kDiag; ++q)
-              if (q < bs) v = v - Td[r][q] * x[q];
-            if (!UNIT) v = v / Td[r][r];
-            x[r] = v;
-          }
+          for (int q = r + 1; q < kDiag; ++q) v = v - Td[r][q] * x[q];
+          if (!UNIT) v = r < bs ? v / Td[r][r] : v;
+          x[r] = v;
         }
       }
 #pragma unroll
-      for (int r = 0; r < kDiag; ++r)
-        if (r < bs) X[(ib + r) * kPitch + tid] = x[r];
+      for (int r = 0; r < kDiag; ++r) X[(ib + r) * kPitch + tid] = x[r];
     }
     __syncthreads();
 #pragma unroll
