@@ -10,6 +10,18 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for the
+// wave's outstanding global loads and stores (the vector memory counter counts
+// both), which defeats loads issued ahead of a barrier for later use and, in
+// the panel kernel, device-coherent stores (about a microsecond per column).
+// For kernels whose waves exchange nothing through global memory inside the
+// workgroup.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------- panel kernel
 // Widest register-resident panel block, the largest number of cooperating
 // workgroups of one panel launch and the tallest panel they hold (the leader

@@ -76,15 +76,6 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 __device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
 
-// Workgroup barrier that orders LDS only.  The waves exchange nothing through
-// global memory inside a workgroup, and a full barrier would also wait for the
-// wave's outstanding device-coherent stores (the vector memory counter counts
-// stores), a round trip of about a microsecond per column.
-__device__ __forceinline__ void lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_max_step(double v) {

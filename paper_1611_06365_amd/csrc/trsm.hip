@@ -10,7 +10,11 @@
 // block, 32 threads solve the block's rows (column by column, T's diagonal
 // block staged in LDS), then the four waves update the rows still to be solved
 // with v_mfma_f64_16x16x4f64 (A = -T from global memory, B = the solved rows,
-// C = the LDS rows).  Taller triangles are processed in 256-row blocks: solve a
+// C = the LDS rows).  A wave owns whole 16-row blocks of the update, so the
+// -T entries of a row are fetched once per step (two 16-byte loads per lane
+// on aligned rows) and feed both 16-column halves; they are requested before
+// the block solve, from clamped addresses with no condition, so they arrive
+// while it runs.  Taller triangles are processed in 256-row blocks: solve a
 // block, then update the rows still to be solved with the matrix-core GEMM.
 #include "mlu_internal.h"
 
@@ -64,7 +68,8 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
   }
 
   const int nblk = (nr + kDiag - 1) / kDiag;
-  constexpr int kItems = 2 * (kRows / 16) / 4;   // update items per wave, at most
+  constexpr int kRB = (kRows / 16) / 4;   // 16-row blocks of the update per wave, at most
+  const bool t_vec = ((reinterpret_cast<uintptr_t>(T) & 15) == 0) && (ldt % 2 == 0);
   // this thread's entry of T's diagonal block, loaded one step ahead
   const int dr = tid / kDiag, dc = tid % kDiag;
   auto diag_entry = [&](int step) {
@@ -73,35 +78,56 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
     return T[(size_t)(blk * kDiag + min(dr, bsz - 1)) * ldt + blk * kDiag + min(dc, bsz - 1)];
   };
   double tdv = diag_entry(0);
+  // The loads are unconditional, from addresses clamped into the triangle
+  // (rows < nr, columns ib..ib+bs-1), and masked where they are used: a
+  // select at issue would make every load wait for its own result.  A lane's
+  // four entries of an item are contiguous (k = 4 lq .. 4 lq + 3), so a full
+  // block on 16-byte aligned rows takes them in two 16-byte loads.
+  auto load_ta = [&](int step, double (&ta)[kRB][4]) {
+    const int blk = LOWER ? step : nblk - 1 - step;
+    const int ib = blk * kDiag;
+    const int bs = min(kDiag, nr - ib);
+    const int rlo = LOWER ? ib + kDiag : 0;
+    if (t_vec && bs == kDiag) {
+#pragma unroll
+      for (int i = 0; i < kRB; ++i) {
+        const int tr = min(rlo + (wave + 4 * i) * 16 + li, nr - 1);
+        const double2* pt = reinterpret_cast<const double2*>(T + (size_t)tr * ldt + ib + 4 * lq);
+        const double2 u0 = pt[0], u1 = pt[1];
+        ta[i][0] = u0.x;
+        ta[i][1] = u0.y;
+        ta[i][2] = u1.x;
+        ta[i][3] = u1.y;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kRB; ++i) {
+        const int tr = min(rlo + (wave + 4 * i) * 16 + li, nr - 1);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = min(4 * lq + st, bs - 1);   // MFMA step st feeds lane group lq with k = 4 lq + st
+          ta[i][st] = T[(size_t)tr * ldt + ib + k];
+        }
+      }
+    }
+  };
+  double ta[kRB][4];
   for (int step = 0; step < nblk; ++step) {
     const int blk = LOWER ? step : nblk - 1 - step;
     const int ib = blk * kDiag;
     const int bs = min(kDiag, nr - ib);
     // rows still to be solved: below the block (lower) or above it (upper);
-    // this wave's update items are (16-row block, 16-column half) pairs, and
-    // their -T entries are fetched now, so the loads overlap the block solve
+    // this wave's 16-row blocks' -T entries are requested now, so the loads
+    // overlap the block solve
     const int rlo = LOWER ? ib + kDiag : 0;
     const int rhi = LOWER ? nr : ib;
     const int nrb = rhi > rlo ? (rhi - rlo + 15) / 16 : 0;
-    // The loads are unconditional, from addresses clamped into the triangle
-    // (rows < nr, columns ib..ib+bs-1), and masked where they are used: a
-    // select at issue would make every load wait for its own result.
-    double ta[kItems][4];
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const int item = wave + 4 * i;
-      const int tr = min(rlo + (item >> 1) * 16 + li, nr - 1);
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int k = min(4 * lq + st, bs - 1);   // MFMA step st feeds lane group lq with k = 4 lq + st
-        ta[i][st] = T[(size_t)tr * ldt + ib + k];
-      }
-    }
+    load_ta(step, ta);
     // T's diagonal block -> LDS (zero outside the block), then the next
     // step's entry is requested
     Td[dr][dc] = (dr < bs && dc < bs) ? tdv : 0.0;
     if (step + 1 < nblk) tdv = diag_entry(step + 1);
-    __syncthreads();
+    lds_sync();
     // solve the block's rows, one column per thread.  No branch on the block
     // size: rows past bs are rows past nr, zero in LDS, and T is zero there,
     // so they only ever subtract exact zeros (and are divided only when
@@ -132,27 +158,37 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
 #pragma unroll
       for (int r = 0; r < kDiag; ++r) X[(ib + r) * kPitch + tid] = x[r];
     }
-    __syncthreads();
+    lds_sync();
+    // each wave updates whole 16-row blocks (wave, wave + 4, ...): both
+    // 16-column halves of a block share its -T operands, as two MFMA chains
 #pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const int item = wave + 4 * i;
-      if (item < 2 * nrb) {
-        const int R0 = rlo + (item >> 1) * 16, ch = (item & 1) * 16;
+    for (int i = 0; i < kRB; ++i) {
+      const int rb = wave + 4 * i;
+      if (rb < nrb) {
+        const int R0 = rlo + rb * 16;
         const bool row_ok = R0 + li < nr;
-        v4d acc;
+        v4d acc0, acc1;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = X[(R0 + lq + 4 * r) * kPitch + ch + li];
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const double b = X[(ib + 4 * lq + st) * kPitch + ch + li];
-          const double a = (row_ok && 4 * lq + st < bs) ? -ta[i][st] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) {
+          acc0[r] = X[(R0 + lq + 4 * r) * kPitch + li];
+          acc1[r] = X[(R0 + lq + 4 * r) * kPitch + 16 + li];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) X[(R0 + lq + 4 * r) * kPitch + ch + li] = acc[r];
+        for (int st = 0; st < 4; ++st) {
+          const double b0 = X[(ib + 4 * lq + st) * kPitch + li];
+          const double b1 = X[(ib + 4 * lq + st) * kPitch + 16 + li];
+          const double a = (row_ok && 4 * lq + st < bs) ? -ta[i][st] : 0.0;
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          X[(R0 + lq + 4 * r) * kPitch + li] = acc0[r];
+          X[(R0 + lq + 4 * r) * kPitch + 16 + li] = acc1[r];
+        }
       }
     }
-    __syncthreads();
+    lds_sync();
   }
 
   for (int e = tid; e < kRows * kCols; e += 256) {
