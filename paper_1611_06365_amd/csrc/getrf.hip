@@ -63,12 +63,12 @@ __global__ void k_et_reset(int32_t* stop, int32_t* width) {
   }
 }
 
-// one library-owned stream and two events per device for the look-ahead fork;
+// one library-owned stream and four events per device for the look-ahead fork;
 // early termination adds one event and a pinned word for the panel width
 struct AuxStreams {
   bool ready = false;
   hipStream_t s1 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr, width_ev = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr, pf2 = nullptr, width_ev = nullptr;
   int32_t* h_width = nullptr;
 };
 
@@ -96,6 +96,7 @@ hipError_t get_aux(AuxStreams** out) {
     if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.ru1, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&a.pf2, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&a.width_ev, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipHostMalloc(reinterpret_cast<void**>(&a.h_width), sizeof(int32_t), hipHostMallocDefault)) !=
         hipSuccess)
@@ -184,20 +185,23 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
     const int bp = (k + 1 < sched.size()) ? sched[k + 1] : 0;
     if (bp > 0) {
       MLU_TRY(hipEventRecord(aux->fork, s0));
-      // T_RU: RU1, then RU2 as a persistent tile queue that leaves CUs to T_PF
-      // (enqueued first, so that it is running while the host is still
-      // enqueueing the panel's many short launches)
+      // T_RU: RU1, then RU2 as a persistent tile queue that leaves CUs to T_PF.
+      // RU2 starts once PF2 is done: PF2's tiles would otherwise take CUs that
+      // the persistent RU2 workgroups cannot get back until they finish,
+      // which costs RU2 more than the wait (measured at n = 16384)
       const int c0 = jn + bp;
       unsigned* q = c.queue->ctr[k % kQueueSlots];
       unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
       if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
       MLU_TRY(hipEventRecord(aux->ru1, s0));
-      const int mr = c.m - jn, nr = c.n - c0;
-      MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
-                         kLaReserve, 0, true, c.prec));
       // T_PF: PF1, PF2, PF3, then it joins RU2's queue (after RU1 is done)
       MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
       MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));         // PF1, PF2
+      MLU_TRY(hipEventRecord(aux->pf2, s1));
+      const int mr = c.m - jn, nr = c.n - c0;
+      MLU_TRY(hipStreamWaitEvent(s0, aux->pf2, 0));
+      MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
+                         kLaReserve, 0, true, c.prec));
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,

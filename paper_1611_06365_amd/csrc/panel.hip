@@ -658,9 +658,21 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ A, int lda, int
       const int cc = tid % kMvCols;
       const int g = c0 + cc;
       const int col = g < cl ? g - cl : bw + (g - cl);   // relative to the block's first column
-      for (int sl = tid / kMvCols; sl < ntouch; sl += NT / kMvCols) {
-        const int src = es.label[sl];
-        if (g < ncols && es.row[sl] >= 0 && src != sl) es.mv[sl][cc] = A[(size_t)es.row[src] * lda + col];
+      // every slot's source is read, from a clamped row and column (an unused
+      // slot's entry is never written back), all loads before the first store
+      const int gc = min(g, ncols - 1);
+      const int colc = gc < cl ? gc - cl : bw + (gc - cl);
+      constexpr int kPer = 2 * kPanelRegCols / (NT / kMvCols);
+      double mvv[kPer];
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int sl = min(tid / kMvCols + t * (NT / kMvCols), ntouch - 1);
+        mvv[t] = A[(size_t)max(es.row[es.label[sl]], 0) * lda + colc];
+      }
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int sl = tid / kMvCols + t * (NT / kMvCols);
+        if (sl < ntouch) es.mv[sl][cc] = mvv[t];
       }
       __syncthreads();
       for (int sl = tid / kMvCols; sl < ntouch; sl += NT / kMvCols) {
