@@ -309,17 +309,20 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
       unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
       if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
       MLU_TRY(hipEventRecord(aux->ru1, s0));
+      MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
+      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));          // PF1, PF2
+      hipLaunchKernelGGL(k_et_reset, dim3(1), dim3(64), 0, s1, &et->stop, &et->width);
+      MLU_TRY(hipGetLastError());
+      MLU_TRY(hipEventRecord(aux->pf2, s1));
+      // RU2 once PF2 is done (as in run_la), then its completion signal
       const int mr = c.m - jn, nr = c.n - c0;
+      MLU_TRY(hipStreamWaitEvent(s0, aux->pf2, 0));
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
                          kLaReserve, 0, true, c.prec));
       if (force != 2) {   // RU2 done: tell the panel
         hipLaunchKernelGGL(k_et_signal, dim3(1), dim3(64), 0, s0, &et->ru_done, k1);
         MLU_TRY(hipGetLastError());
       }
-      MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
-      MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));          // PF1, PF2
-      hipLaunchKernelGGL(k_et_reset, dim3(1), dim3(64), 0, s1, &et->stop, &et->width);
-      MLU_TRY(hipGetLastError());
       if (force == 1) {   // as if RU2 had finished before the panel started
         hipLaunchKernelGGL(k_et_signal, dim3(1), dim3(64), 0, s1, &et->ru_done, k1);
         MLU_TRY(hipGetLastError());
