@@ -614,9 +614,15 @@ struct EpilogueShared {
 
 // Kept out of line so that its registers do not add to the factorization's;
 // es.L already holds the block's strictly lower rows 0..bw-1.
+typedef __attribute__((address_space(1))) double gdouble;   // global memory
+
 template <int BW>
-__device__ __noinline__ void panel_epilogue(double* __restrict__ A, int lda, int bw, int cl, int cr,
+__device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, int bw, int cl, int cr,
                                             const int* piv, int tid, EpilogueShared* esp) {
+  // the matrix is global memory: accessed as such, the loads and stores are
+  // global (vector-memory counter only) instead of flat, which would also
+  // count against the LDS counter that every LDS wait below waits for
+  gdouble* __restrict__ A = (gdouble*)Ag;
   EpilogueShared& es = *esp;
   const int ntouch = 2 * bw;
   if (tid < ntouch) {
@@ -685,7 +691,7 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ A, int lda, int
   // A12 := trilu(A11)^-1 A12 on the right columns, one column per thread
   for (int j = tid; j < cr; j += NT) {
     double x[BW];
-    double* colp = A + bw + j;
+    gdouble* colp = A + bw + j;
 #pragma unroll
     for (int r = 0; r < BW; ++r) x[r] = (r < bw) ? colp[(size_t)r * lda] : 0.0;
 #pragma unroll
