@@ -14,8 +14,11 @@
  *    caller; h_ pointers are host memory read during the call only.  The
  *    library never allocates or frees device memory in these calls.
  *  * `stream` is a hipStream_t (NULL = the default stream).  All device work is
- *    enqueued on it asynchronously; nothing synchronizes.  Results (including
- *    *d_info) are valid once the stream's work has completed.  The look-ahead
+ *    enqueued on it asynchronously; nothing synchronizes, except the two entry
+ *    points whose loop is decided on the host (mlu_dgetrf_et waits for each
+ *    panel's realized width, mlu_dsgesv_gmres_ir for each refinement and GMRES
+ *    step), as documented there.  Results (including *d_info) are valid once
+ *    the stream's work has completed.  The look-ahead
  *    variant additionally uses one library-owned stream per device (default
  *    priority), forked from and joined back into `stream` with events, so a
  *    caller's stream capture records the whole call.
@@ -96,8 +99,9 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
  *
  *  stream      hipStream_t.
  *  m, n        matrix size.
- *  dA, lda     device matrix, row-major, lda >= max(1, n); m <= 32768 (the
- *              tallest panel the register-resident kernel holds).
+ *  dA, lda     device matrix, row-major, lda >= max(1, n); m <= 33280
+ *              (512 + 32 * 1024 rows: the tallest panel the register-resident
+ *              kernel holds).
  *  d_ipiv      device int32[min(m, n)].
  *  d_info      device int32[1].
  *  variant     MLU_RL, MLU_LL or MLU_LA.
@@ -220,7 +224,8 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
  *  *h_outer = corrections applied when berr <= tol was reached (0 if the first
  *  solve met it), or -1 if max_outer corrections did not reach it;
  *  *h_inner = GMRES steps over all corrections; *h_berr = berr of the x
- *  returned.  1 <= max_krylov <= MLU_GMRES_MAX_KRYLOV; n <= 32768.
+ *  returned.  1 <= max_krylov <= MLU_GMRES_MAX_KRYLOV; n <= 33280 (as
+ *  mlu_dgetrf).
  *  d_work: mlu_dsgesv_gmres_ir_workspace(n, max_krylov) bytes (the n x n
  *  factors and the Krylov basis).  Returns 0, -i for an invalid argument i,
  *  or MLU_ERR_HIP.
