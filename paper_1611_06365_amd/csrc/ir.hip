@@ -1,11 +1,17 @@
 // Mixed-precision LU with FP64 iterative refinement (the precision ladder over
-// the paper's LU variants): factor with FP32 products in the outer trailing
-// updates (mlu_dsgetrf), solve, then refine with FP64 residuals on the GPU:
+// the paper's LU variants): factor with FP32 or BF16 products in the outer
+// trailing updates (mlu_dsgetrf), solve, then refine with FP64 residuals on
+// the GPU:
 //   r = b - A x (FP64),  berr = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf),
-//   stop when berr <= tol, else solve (LU) d = P r and x := x + d.
-// Everything is enqueued on the caller's stream; convergence is a device flag
-// that the remaining launches of the refinement loop read, so that they do
-// nothing once it is raised (no host synchronization).
+//   stop when berr <= tol, else x := x + d with a correction d.
+// mlu_dsgesv_ir (LU-IR): d = (LU)^-1 P r; everything is enqueued on the
+// caller's stream, convergence is a device flag that the remaining launches
+// of the refinement loop read, so that they do nothing once it is raised (no
+// host synchronization).
+// mlu_dsgesv_gmres_ir (GMRES-IR, Carson and Higham): d from GMRES on the
+// LU-preconditioned system (below), or LU-IR corrections, or LU-IR until it
+// stops halving berr; the host drives the loop and reads a small state after
+// each step.
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
 
