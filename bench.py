@@ -232,6 +232,51 @@ def et_section(args, A, ipiv, info, work):
             "n": A.shape[0], "matrix": args.matrix, "rows": rows}
 
 
+def schedule_section(args, A, ipiv, info, work):
+    """The block size chosen per iteration (the "determine block size" step of
+    the loop): the bench's variant with blocks of 2 nb over the first 3/8 of the
+    order, then nb, beside constant nb, on the bench matrix.  Each run factors a
+    fresh copy of A (restored outside the timed region); the two forms
+    alternate, best of three each after a warm-up.  Not the headline figure,
+    whose workload fixes nb."""
+    import torch
+
+    from paper_1611_06365_amd import mlu
+
+    n = A.shape[0]
+    lead = 2 * args.nb
+    count = max(1, (3 * n // 8) // lead)
+    sched = [lead] * count
+    M = torch.empty_like(A)
+
+    def run(schedule):
+        M.copy_(A)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mlu.getrf(M, variant=args.variant, nb=args.nb, nb_inner=args.nb_inner, schedule=schedule, ipiv=ipiv,
+                  info=info, work=work)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run(None)
+    run(sched)
+    const_ms, sched_ms = [], []
+    for _ in range(3):
+        const_ms.append(run(None))
+        sched_ms.append(run(sched))
+    out = {"what": f"{args.variant.upper()} with {count} blocks of {lead} then {args.nb}, vs constant nb={args.nb}",
+           "schedule": sched, "nb_after": args.nb,
+           "ms_constant": round(min(const_ms), 3), "ms_schedule": round(min(sched_ms), 3),
+           "gflops_schedule": round(2.0 * n ** 3 / 3.0 / (min(sched_ms) / 1e3) / 1e9, 1),
+           "speedup": round(min(const_ms) / min(sched_ms), 4),
+           "info": int(info.item()), "sampled_residual": sampled_residual(A, M, ipiv)}
+    log(f"schedule: {out}")
+    del M
+    return out
+
+
 def grid_section(args, dev):
     """Every variant at n in {4096, 8192, 16384} and nb in {64, 128, 256} (b_i =
     16) on A = B B^T + n I (seed 0): one warm-up, then the best of two timed
@@ -423,6 +468,7 @@ def main() -> int:
     ap.add_argument("--max-krylov", type=int, default=200, help="GMRES-IR Krylov dimension limit")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
     ap.add_argument("--no-et", action="store_true", help="skip the early-termination comparison")
+    ap.add_argument("--no-schedule", action="store_true", help="skip the per-iteration block-size comparison")
     ap.add_argument("--grid", action="store_true",
                     help="also time every variant at n in {4096, 8192, 16384} x nb in {64, 128, 256}")
     ap.add_argument("--batch", type=int, default=20000)
@@ -532,6 +578,10 @@ def main() -> int:
     if not args.no_et:
         et = et_section(args, A, ipiv, info, work)
 
+    blocks = None
+    if not args.no_schedule:
+        blocks = schedule_section(args, A, ipiv, info, work)
+
     batched = None
     if not args.no_batched:
         batched = batched_section(args, dev)
@@ -575,6 +625,7 @@ def main() -> int:
         "roofline": roof,
         "mixed": mixed,
         "early_termination": et,
+        "block_schedule": blocks,
         "selector": sel,
         "grid": grid,
         "batched": batched,
