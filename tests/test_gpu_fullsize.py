@@ -19,6 +19,9 @@ an n x n random part), and single entries of U deep in the factorization move
 by more (1.2e-12 to 1.5e-12 of max|F_oracle| measured), so the bar there is
 normwise, ||F - F_oracle||_F / ||F_oracle||_F <= 1e-12 (2.3e-13 measured),
 with an elementwise guard of 1e-10 * max|F_oracle|.
+The block size chosen per iteration (blocks of 2 nb over the first 3/8 of
+the order, then nb: the schedule the benchmark also times) is held to the
+same bars.
 """
 import numpy as np
 import pytest
@@ -69,9 +72,9 @@ def properties(A, F, ipiv):
     return res, lmax
 
 
-def factor(A, variant, nb):
+def factor(A, variant, nb, schedule=None):
     F = A.clone()
-    ipiv, info = mlu.getrf(F, variant=variant, nb=nb, nb_inner=16)
+    ipiv, info = mlu.getrf(F, variant=variant, nb=nb, nb_inner=16, schedule=schedule)
     torch.cuda.synchronize()
     return F, ipiv, int(info.item())
 
@@ -124,3 +127,40 @@ def test_n4096_against_c_oracle(recipe, variant, nb):
         assert err <= 1e-12
     else:
         assert nerr <= 1e-12 and err <= 1e-10
+
+
+def lead_schedule(n, nb):
+    """Blocks of 2 nb over the first 3/8 of the order (then nb)."""
+    return [2 * nb] * max(1, (3 * n // 8) // (2 * nb))
+
+
+@pytest.mark.parametrize("recipe", ["spd", "uniform"])
+def test_fullsize_block_schedule(recipe):
+    n, nb = 16384, 256
+    A = matrix(recipe, n)
+    sched = lead_schedule(n, nb)
+    assert sched == [512] * 12
+    F, ipiv, info = factor(A, "la", nb, schedule=sched)
+    assert info == 0
+    res, lmax = properties(A, F, ipiv)
+    print(f"{recipe} n={n} la schedule 512x12 then {nb}: residual {res:.2e} max|L| {lmax:.3f}", flush=True)
+    assert res <= 1e-13 and lmax <= 1.0
+
+
+@pytest.mark.parametrize("variant", ["rl", "la"])
+def test_n4096_block_schedule_against_c_oracle(variant):
+    n, nb = 4096, 256
+    A = matrix("spd", n)
+    if "spd" not in _oracle:
+        R = np.ascontiguousarray(A.cpu().numpy())
+        opiv, oinfo = c_oracle.dgetrf_rl(R, nb=64)
+        _oracle["spd"] = (R, opiv, oinfo)
+    R, opiv, oinfo = _oracle["spd"]
+    sched = lead_schedule(n, nb)
+    assert sched == [512] * 3
+    F, ipiv, info = factor(A, variant, nb, schedule=sched)
+    assert info == oinfo == 0
+    assert np.array_equal(ipiv.cpu().numpy(), opiv)
+    err = float(np.abs(F.cpu().numpy() - R).max() / np.abs(R).max())
+    print(f"spd n=4096 {variant} schedule 512x3 then {nb}: max|F - oracle| / max|oracle| = {err:.2e}", flush=True)
+    assert err <= 1e-12
