@@ -232,6 +232,11 @@ def et_section(args, A, ipiv, info, work):
             "n": A.shape[0], "matrix": args.matrix, "rows": rows}
 
 
+def lead_schedule(n: int, nb: int):
+    """Blocks of 2 nb over the first 3/8 of the order (then nb)."""
+    return [2 * nb] * max(1, (3 * n // 8) // (2 * nb))
+
+
 def schedule_section(args, A, ipiv, info, work):
     """The block size chosen per iteration (the "determine block size" step of
     the loop): the bench's variant with blocks of 2 nb over the first 3/8 of the
@@ -244,9 +249,8 @@ def schedule_section(args, A, ipiv, info, work):
     from paper_1611_06365_amd import mlu
 
     n = A.shape[0]
-    lead = 2 * args.nb
-    count = max(1, (3 * n // 8) // lead)
-    sched = [lead] * count
+    sched = lead_schedule(n, args.nb)
+    lead, count = sched[0], len(sched)
     M = torch.empty_like(A)
 
     def run(schedule):

@@ -28,6 +28,7 @@ import pytest
 import torch
 
 import inputs.device as D
+from bench import lead_schedule
 from oracle import c_oracle
 from paper_1611_06365_amd import mlu
 
@@ -127,11 +128,6 @@ def test_n4096_against_c_oracle(recipe, variant, nb):
         assert err <= 1e-12
     else:
         assert nerr <= 1e-12 and err <= 1e-10
-
-
-def lead_schedule(n, nb):
-    """Blocks of 2 nb over the first 3/8 of the order (then nb)."""
-    return [2 * nb] * max(1, (3 * n // 8) // (2 * nb))
 
 
 @pytest.mark.parametrize("recipe", ["spd", "uniform"])
