@@ -70,15 +70,28 @@ enum mlu_precision {
 /* Largest order of a matrix in the batched factorization. */
 #define MLU_BATCH_MAX_N 512
 
-/* Largest panel block held in registers by the diagonal-block kernel. */
-#define MLU_MAX_NB_INNER 16
+/* Largest inner block size b_i of the panel factorization (Section 4.2 uses
+ * b_i = 16 and 32).  The diagonal-block kernel holds 16 columns in registers;
+ * a 32-column block is eliminated by it in two passes. */
+#define MLU_MAX_NB_INNER 32
 
-/* Library version, e.g. 100 for 0.1.0. */
+/* Library version, e.g. 200 for 0.2.0. */
 int mlu_version(void);
 
 /*
+ * Prepare the library on the current device: the look-ahead variant's
+ * library-owned stream and events, created once per device.  Called by the
+ * workspace queries; a caller that captures a look-ahead call into a graph
+ * calls it (or a workspace query) on that device before the capture, since
+ * the creation is not a stream operation.  Returns 0 or MLU_ERR_HIP.
+ */
+int mlu_init(void);
+
+/*
  * Workspace (device bytes) that mlu_dgetrf needs.  Depends on nothing but the
- * library build; arguments are accepted for forward compatibility.
+ * library build; arguments are accepted for forward compatibility.  Also runs
+ * mlu_init on the current device (its failure is not reported here: without a
+ * device the size is still returned).
  * Returns 0, or -i for an invalid argument; *bytes receives the size.
  */
 int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t *bytes);
@@ -107,10 +120,21 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
  *  variant     MLU_RL, MLU_LL or MLU_LA.
  *  nb          outer block size b (>= 1); nb = 1 gives each variant's
  *              unblocked form, nb >= min(m,n) a single panel.
- *  nb_inner    block size b_i of the panel factorization, 0..16 (0 = min(nb,
- *              16)): the panel [A11; A21] is factored by the blocked RL
- *              algorithm with b_i, each b_i-column block by the
- *              register-resident unblocked kernel; b_i >= b means LU_unb.
+ *  nb_inner    block size b_i of the panel factorization, 0..32 (0 = min(nb,
+ *              16)): the panel [A11; A21] is factored by the blocked `inner`
+ *              algorithm with b_i, each b_i-column block by LU_unb in the
+ *              register-resident diagonal-block kernel (16 columns per pass;
+ *              a block of 17..32 columns takes two passes with a rank-16
+ *              update between them, the same elimination); b_i >= b means
+ *              LU_unb on the whole panel.
+ *  inner       algorithm of the panel factorization (Section 4.2, "outer /
+ *              inner LU"): MLU_RL (right-looking: after each b_i block its
+ *              interchanges, the solve of its rows and the update of the
+ *              panel's columns to its right) or MLU_LL (left-looking: each
+ *              b_i block first receives the panel's earlier interchanges, then
+ *              the solve and update with the panel's columns to its left, then
+ *              its own factorization, whose interchanges go to the columns to
+ *              its left only).  Both give the same factors up to rounding.
  *  h_schedule  optional host array of n_schedule block sizes (each >= 1) used
  *              for the first outer iterations instead of nb (the paper's
  *              "Determine block size b"; the last block is trimmed to what is
@@ -123,7 +147,7 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
  *  d_work      device workspace of work_bytes >= mlu_dgetrf_workspace().
  */
 int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
-               int variant, int nb, int nb_inner, const int32_t *h_schedule, int n_schedule,
+               int variant, int nb, int nb_inner, int inner, const int32_t *h_schedule, int n_schedule,
                int iters_limit, void *d_work, size_t work_bytes);
 
 /*
@@ -167,28 +191,30 @@ int mlu_dgetrf_et(void *stream, int m, int n, double *dA, int lda, int32_t *d_ip
  * as the factorization inside iterative refinement (mlu_dsgesv_ir), the
  * precision ladder the paper's loop-based variants admit unchanged (Fig.
  * "LU", Fig. "LU_la_blk": only the update kernel differs).  Arguments as
- * mlu_dgetrf, with `precision` inserted as argument 11 (later arguments are
+ * mlu_dgetrf, with `precision` inserted as argument 12 (later arguments are
  * numbered one higher in the -i return codes).
  */
 int mlu_dsgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info, int variant,
-                int nb, int nb_inner, int precision, const int32_t *h_schedule, int n_schedule, int iters_limit,
-                void *d_work, size_t work_bytes);
+                int nb, int nb_inner, int inner, int precision, const int32_t *h_schedule, int n_schedule,
+                int iters_limit, void *d_work, size_t work_bytes);
 
 /*
  * Solve A X = B by mixed-precision LU and FP64 iterative refinement (the
  * precision ladder over the paper's variants; Section 3 for the
  * factorization):
- *   LU := A factored by mlu_dsgetrf(precision, variant, nb, nb_inner);
+ *   LU := A factored by mlu_dsgetrf(precision, variant, nb, nb_inner, MLU_RL);
  *   X  := U^-1 L^-1 P B;
  *   repeat: R := B - A X in FP64;
  *           berr := max_j ||R_j||_inf / (||A||_inf ||X_j||_inf + ||B_j||_inf);
- *           stop if berr <= tol (or after max_iter corrections);
+ *           stop if berr <= tol (or after max_iter corrections, or once
+ *             berr is not finite or above twice the smallest berr so far:
+ *             the corrections diverge);
  *           X := X + U^-1 L^-1 P R.
  *  dA (n x n, lda), dB (n x nrhs, ldb): read only.  dX (n x nrhs, ldx): the
  *  solution.  d_ipiv (int32[n]) and d_info as mlu_dgetrf, for the factors.
  *  *d_iters = number of corrections applied when berr <= tol was reached (0 if
- *  the first solve met it), or -1 if it was not reached after max_iter
- *  corrections; *d_berr = berr of the X returned.  Everything is enqueued;
+ *  the first solve met it), or -1 if it was not reached (max_iter corrections,
+ *  or divergence); *d_berr = berr of the X returned.  Everything is enqueued;
  *  the stop test is a device flag that the rest of the enqueued loop reads.
  *  d_work: mlu_dsgesv_ir_workspace(n, nrhs) bytes (it holds the n x n factors).
  *  Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
@@ -204,13 +230,14 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
  * refinement whose corrections may come from GMRES (GMRES-IR: Carson and
  * Higham, SIAM J. Sci. Comput. 2017 and 2018), for kappa(A) * u_low >~ 1,
  * where the plain corrections of mlu_dsgesv_ir stop converging.  M = P^T L U is
- * the factorization of mlu_dsgetrf(precision, variant, nb, nb_inner) (Section 3),
+ * the factorization of mlu_dsgetrf(precision, variant, nb, nb_inner, MLU_RL) (Section 3),
  * applied in FP64 as the preconditioner.
  *   x := M^-1 b;
  *   repeat: r := b - A x in FP64;
  *           berr := ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf);
  *           stop if berr <= tol (or after max_outer corrections);
- *           solver MLU_IR_LU:    d := M^-1 r;
+ *           solver MLU_IR_LU:    d := M^-1 r (stopping as not converged
+ *             once berr is not finite or above twice the smallest so far);
  *           solver MLU_IR_GMRES: d := GMRES on M^-1 A d = M^-1 r from d = 0,
  *             Arnoldi with classical Gram-Schmidt applied twice, Givens
  *             rotations; it stops when its residual estimate falls to
@@ -270,21 +297,36 @@ int mlu_sgetrf_batched(void *stream, int batch, const int32_t *d_n, float *const
                        size_t work_bytes);
 
 /*
- * The learned selector (the block-size study of Section 5.1 as a model): given
- * the order n and the product precision, choose the variant and the outer
- * block size b for mlu_dgetrf / mlu_dsgetrf.  Host function, no device work.
- *  model       host float array written by the selector's pack(): header
- *              [3, hidden, n_out, 3], n_out (variant, b) pairs, then three
- *              dense layers (row-major W, then b) of a 3 -> hidden -> hidden
- *              -> n_out perceptron with ReLU; outputs are predicted log
- *              times, the smallest wins (first on ties).
+ * The learned selector (the block-size study of Section 5.1 as a model):
+ * given the order n, the number of matrices and the product precision,
+ * choose the variant and block size.  Host function, no device work.
+ *  model       host float array written by the selector's pack(): a header
+ *              [2, 9, hidden, 3, n_cand, n_lo, n_hi, batch_hi, margin, sd,
+ *              ll_max_panels, batch_max_n], n_cand (variant id, b) candidate
+ *              pairs (variant id 0..2 = MLU_RL/LL/LA with outer block size b
+ *              for mlu_dgetrf / mlu_dsgetrf, 3 = MLU_SELECT_BATCHED with panel
+ *              width b for mlu_?getrf_batched), then three dense layers
+ *              (row-major W, then b) of a 9 -> hidden -> hidden -> 1
+ *              perceptron with ReLU predicting the scaled log time per flop
+ *              of one configuration from its features (log2 n, its square,
+ *              log2 batch, the FP32 flag, the variant one-hot, log2 b).
  *  model_len   its length in floats.
- *  n           matrix order (>= 1); precision MLU_PREC_FP64 or _FP32.
- *  variant, nb receive the choice.
+ *  n           matrix order (>= 1); batch: number of matrices (>= 1);
+ *              precision MLU_PREC_FP64 or _FP32.
+ *  variant, nb receive the choice: the candidate with the smallest
+ *              prediction (the first on ties) among the batched ones when
+ *              batch > 1 and n <= batch_max_n, else among the single-matrix
+ *              ones (the left-looking variant only up to ll_max_panels
+ *              panels).
+ *  fallback    receives 1 when the exhaustive autotuner should decide instead
+ *              (n outside [n_lo, n_hi] or batch above batch_hi, or the
+ *              runner-up predicted within `margin` of the choice), else 0.
  * Returns 0 or -i for an invalid argument i (a malformed model is argument 1
  * or 2).
  */
-int mlu_select(const float *model, int model_len, int n, int precision, int *variant, int *nb);
+#define MLU_SELECT_BATCHED 3
+int mlu_select(const float *model, int model_len, int n, int batch, int precision, int *variant, int *nb,
+               int *fallback);
 
 /*
  * Triangular solve with several right-hand sides, left side, no transpose:
@@ -337,11 +379,15 @@ int mlu_dgetf2_block(void *stream, int m, int bw, double *dA, int lda, int32_t *
  * (RL3, PF2, RU2 -- the kernel that carries nearly all of the flops).
  * mlu_trace_begin(capacity) makes every following such launch, on any stream,
  * record a pair of HIP events around itself (at most `capacity` launches; the
- * library creates the events once).  mlu_trace_end waits for the recorded
- * events and returns the number of launches timed, their summed duration in
- * ms, and their algorithmic flops (2 m n k per launch) and bytes
- * (8 (2 m n + m k + k n) per launch); it stops the recording.  Process-wide
- * state: not for use while another thread factors.
+ * library creates the events once).  In the look-ahead variant, the helper
+ * workgroups that join RU2's tile queue from the panel's stream (Section 4.1,
+ * worker sharing) record a pair too: when they start before RU2's own launch
+ * ends, RU2 counts until the later of the two ends (its last tile may be a
+ * helper's).  mlu_trace_end waits for the recorded events and returns the
+ * number of launches timed, their summed duration in ms, and their
+ * algorithmic flops (2 m n k per launch) and bytes (8 (2 m n + m k + k n) per
+ * launch); it stops the recording.  Process-wide state: not for use while
+ * another thread factors.
  */
 int mlu_trace_begin(int capacity);
 int mlu_trace_end(int *launches, double *total_ms, double *flops, double *bytes);

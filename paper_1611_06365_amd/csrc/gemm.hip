@@ -686,26 +686,44 @@ __global__ __launch_bounds__(256, 2) void k_gemm_queue(int m, int n, int k, cons
 }
 
 // Event timing of the outer trailing-update launches (see mlu_trace_begin).
+// Each traced launch has four events: its start and end on its own stream,
+// and, when helper workgroups on another stream join its tile queue, one
+// before and one after the helper launch (kEv events per slot).
+constexpr int kEv = 4;
 struct Trace {
   std::mutex mu;
   bool on = false;
   int cap = 0, used = 0;
   std::vector<hipEvent_t> ev;
+  std::vector<char> tail;
   double flops = 0.0, bytes = 0.0;
 };
 Trace g_trace;
 
-// The event pair for one traced launch of an m x n x k update (none once the
-// capacity is used up or no trace is active).
-void trace_slot(int m, int n, int k, hipEvent_t* e0, hipEvent_t* e1) {
+// The start / end events of one traced launch of an m x n x k update and its
+// slot number (none, -1, once the capacity is used up or no trace is active).
+int trace_slot(int m, int n, int k, hipEvent_t* e0, hipEvent_t* e1) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
   if (g_trace.on && g_trace.used < g_trace.cap) {
-    *e0 = g_trace.ev[2 * g_trace.used];
-    *e1 = g_trace.ev[2 * g_trace.used + 1];
-    ++g_trace.used;
+    const int id = g_trace.used++;
+    *e0 = g_trace.ev[kEv * id];
+    *e1 = g_trace.ev[kEv * id + 1];
+    g_trace.tail[id] = 0;
     g_trace.flops += 2.0 * m * (double)n * k;
     g_trace.bytes += 8.0 * (2.0 * m * (double)n + (double)m * k + (double)k * n);
+    return id;
   }
+  return -1;
+}
+
+// The events around a helper launch that joins traced launch `id`'s queue.
+bool trace_tail(int id, hipEvent_t* pre, hipEvent_t* post) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  if (id < 0 || id >= g_trace.used) return false;
+  *pre = g_trace.ev[kEv * id + 2];
+  *post = g_trace.ev[kEv * id + 3];
+  g_trace.tail[id] = 1;
+  return true;
 }
 
 }  // namespace
@@ -722,7 +740,7 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
   const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
                    (lda % 2 == 0) && (ldb % 2 == 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (trailing && traced) trace_slot(m, n, k, &e0, &e1);
+  if (trailing && traced) (void)trace_slot(m, n, k, &e0, &e1);
   if (e0) {
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
@@ -758,7 +776,8 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                       double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
-                      int prec) {
+                      int prec, int* trace_id, int tail_of) {
+  if (trace_id != nullptr) *trace_id = -1;
   if (prec != kPrecF64 && prec != kPrecF32 && prec != kPrecBF16) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) {
     if (clear == nullptr) return hipSuccess;
@@ -782,7 +801,12 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
     grid = 2 * cus;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (traced && tiles > 0) trace_slot(m, n, k, &e0, &e1);
+  if (traced && tiles > 0) {
+    const int id = trace_slot(m, n, k, &e0, &e1);
+    if (trace_id != nullptr) *trace_id = id;
+  } else if (tail_of >= 0 && !trace_tail(tail_of, &e0, &e1)) {
+    e0 = e1 = nullptr;
+  }
   if (e0) {
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
@@ -816,12 +840,13 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
 
 hipError_t trace_begin(int capacity) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
-  while ((int)g_trace.ev.size() < 2 * capacity) {
+  while ((int)g_trace.ev.size() < kEv * capacity) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
     g_trace.ev.push_back(e);
   }
+  if ((int)g_trace.tail.size() < capacity) g_trace.tail.resize(capacity);
   g_trace.cap = capacity;
   g_trace.used = 0;
   g_trace.flops = g_trace.bytes = 0.0;
@@ -832,13 +857,25 @@ hipError_t trace_begin(int capacity) {
 hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
   g_trace.on = false;
+  // A launch lasts from its start to its end, unless helpers joined its queue
+  // before it ended (the event before the helper launch precedes its end):
+  // then to the later of its end and the helpers' end.  Helpers that start
+  // after it ended find the queue empty and add nothing.
   double total = 0.0;
   for (int i = 0; i < g_trace.used; ++i) {
-    hipError_t r = hipEventSynchronize(g_trace.ev[2 * i + 1]);
+    const hipEvent_t* ev = &g_trace.ev[kEv * i];
+    hipError_t r = hipEventSynchronize(ev[1]);
     if (r != hipSuccess) return r;
     float t = 0.f;
-    r = hipEventElapsedTime(&t, g_trace.ev[2 * i], g_trace.ev[2 * i + 1]);
+    r = hipEventElapsedTime(&t, ev[0], ev[1]);
     if (r != hipSuccess) return r;
+    if (g_trace.tail[i]) {
+      float tp = 0.f, tq = 0.f;
+      if ((r = hipEventSynchronize(ev[3])) != hipSuccess) return r;
+      if ((r = hipEventElapsedTime(&tp, ev[0], ev[2])) != hipSuccess) return r;
+      if ((r = hipEventElapsedTime(&tq, ev[0], ev[3])) != hipSuccess) return r;
+      if (tp < t && tq > t) t = tq;
+    }
     total += t;
   }
   *launches = g_trace.used;

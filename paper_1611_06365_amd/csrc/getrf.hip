@@ -18,9 +18,10 @@
 //  (Section 4.2, Fig.          stops when RU2 signals; the width it reached
 //  "LU_LA_ET")                 is the next block size
 //
-// The panel [A11; A21] is itself factored by the blocked RL algorithm with the
-// inner block size b_i <= 16, each b_i-wide block by the register-resident
-// kernel (the paper's outer / inner LU, Section 4.2).
+// The panel [A11; A21] is itself factored by the blocked RL or LL algorithm
+// with the inner block size b_i <= 32 (the paper's outer / inner LU, Section
+// 4.2), each b_i-wide block by the register-resident kernel (a block wider
+// than its 16 register columns in two passes).
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
 
@@ -64,12 +65,15 @@ __global__ void k_et_reset(int32_t* stop, int32_t* width) {
 }
 
 // one library-owned stream and four events per device for the look-ahead fork;
-// early termination adds one event and a pinned word for the panel width
+// early termination adds one event and a pinned word for the panel width.
+// `run` is held while one call enqueues its fork / join sequence, so that two
+// host threads factoring on one device do not interleave their event records.
 struct AuxStreams {
   bool ready = false;
   hipStream_t s1 = nullptr;
   hipEvent_t fork = nullptr, join = nullptr, ru1 = nullptr, pf2 = nullptr, width_ev = nullptr;
   int32_t* h_width = nullptr;
+  std::mutex run;
 };
 
 // Look-ahead overlap: RU2 leaves the CUs with id < kLaReserve (mod 8) in every
@@ -123,21 +127,49 @@ struct Ctx {
   QueueWork* queue;
   int prec;          // product precision of the outer trailing updates
   unsigned* epoch;   // panel launch counter of this call (panels run one at a time)
+  int inner;         // algorithm of the panel factorization: MLU_RL or MLU_LL
   double* at(int i, int j) const { return A + (size_t)i * lda + j; }
 };
 
-// RL1 / PF3 / LL3: factor the panel rows j..m-1, columns j..j+b-1 (blocked RL
-// with b_i-wide register-resident blocks); its interchanges are applied to the
-// panel's own columns only.
+// LU_unb of the bw-column diagonal block at (jj, jj), bw <= 32 (Fig. "LU",
+// left), inside a panel with cl columns to the block's left and cr to its
+// right: the block's interchanges are applied to all of them, and the block's
+// rows of the first ns right columns are solved with its unit lower triangle
+// (the inner RL2).  A block wider than the register-resident kernel's 16
+// columns is eliminated in two register passes, right-looking over its
+// columns: the first 16 columns (their rows of the other half solved), a
+// rank-16 update of the other half, then that half; the second pass solves
+// the right columns with the whole 32 x 32 triangle.
+hipError_t factor_block(hipStream_t s, const Ctx& c, int jj, int bw, int cl, int cr, int ns,
+                        const int32_t* skip = nullptr) {
+  if (bw <= kPanelRegCols)
+    return panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, cl, cr, skip,
+                        ns);
+  const int h1 = kPanelRegCols, h2 = bw - kPanelRegCols;
+  MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, h1, jj, c.ipiv, c.info, c.work, ++*c.epoch, cl, h2 + cr,
+                       skip, h2));
+  const int j2 = jj + h1;
+  if (j2 < c.m)
+    MLU_TRY(gemm_update(s, c.m - j2, h2, h1, c.at(j2, jj), c.lda, c.at(jj, j2), c.lda, c.at(j2, j2), c.lda, false,
+                        kPrecF64, false, skip));
+  return panel_factor(s, c.at(j2, j2), c.lda, c.m - j2, h2, j2, c.ipiv, c.info, c.work, ++*c.epoch, cl + h1, cr,
+                      skip, ns, ns > 0 ? h1 : 0);
+}
+
+hipError_t factor_panel_ll(hipStream_t s, const Ctx& c, int j, int b, EtWork* et, unsigned k1, int min_cols);
+
+// RL1 / PF3 / LL3: factor the panel rows j..m-1, columns j..j+b-1 by the
+// inner variant with b_i-wide register-resident blocks; its interchanges are
+// applied to the panel's own columns only.
 hipError_t factor_panel(hipStream_t s, const Ctx& c, int j, int b) {
+  if (c.inner == MLU_LL) return factor_panel_ll(s, c, j, b, nullptr, 0, 0);
   for (int jj = j; jj < j + b; jj += c.bi) {
     const int bw = (j + b - jj) < c.bi ? (j + b - jj) : c.bi;
     // the register-resident kernel also applies the block's interchanges to
     // the panel's other columns and solves the block's rows of the columns to
     // its right (the inner RL2); the inner RL3 follows
     const int rest = j + b - jj - bw;
-    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, jj - j,
-                         rest));
+    MLU_TRY(factor_block(s, c, jj, bw, jj - j, rest, rest));
     if (rest > 0 && jj + bw < c.m)
       MLU_TRY(gemm_update(s, c.m - jj - bw, rest, bw, c.at(jj + bw, jj), c.lda, c.at(jj, jj + bw), c.lda,
                           c.at(jj + bw, jj + bw), c.lda));
@@ -171,6 +203,7 @@ hipError_t run_rl(hipStream_t s, const Ctx& c, const std::vector<int>& sched, in
 hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, int limit) {
   AuxStreams* aux = nullptr;
   MLU_TRY(get_aux(&aux));
+  std::lock_guard<std::mutex> lk(aux->run);
   hipStream_t s1 = aux->s1;
   if (sched.empty()) return hipSuccess;
   int b = sched[0];
@@ -200,12 +233,13 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       MLU_TRY(hipEventRecord(aux->pf2, s1));
       const int mr = c.m - jn, nr = c.n - c0;
       MLU_TRY(hipStreamWaitEvent(s0, aux->pf2, 0));
+      int tid = -1;
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
-                         kLaReserve, 0, true, c.prec));
+                         kLaReserve, 0, true, c.prec, &tid));
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false, c.prec));
+                         0, kLaHelpers, false, c.prec, nullptr, tid));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
     } else {
@@ -270,8 +304,7 @@ hipError_t factor_panel_ll(hipStream_t s, const Ctx& c, int j, int b, EtWork* et
         MLU_TRY(gemm_update(s, c.m - jj, bw, jj - j, c.at(jj, j), c.lda, c.at(j, jj), c.lda, c.at(jj, jj),
                             c.lda, false, kPrecF64, false, skip));                                        // LL2
     }
-    MLU_TRY(panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, jj - j, 0,
-                         skip));                                                                          // LL3
+    MLU_TRY(factor_block(s, c, jj, bw, jj - j, 0, 0, skip));                                             // LL3
     if (et != nullptr) {
       hipLaunchKernelGGL(k_et_check, dim3(1), dim3(64), 0, s, &et->ru_done, k1, &et->stop, &et->width,
                          jj + bw - j, min_cols);
@@ -290,6 +323,7 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
                      std::vector<int>* widths) {
   AuxStreams* aux = nullptr;
   MLU_TRY(get_aux(&aux));
+  std::lock_guard<std::mutex> lk(aux->run);
   hipStream_t s1 = aux->s1;
   const int mn = c.m < c.n ? c.m : c.n;
   int b = nb < mn ? nb : mn;
@@ -317,8 +351,9 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
       // RU2 once PF2 is done (as in run_la), then its completion signal
       const int mr = c.m - jn, nr = c.n - c0;
       MLU_TRY(hipStreamWaitEvent(s0, aux->pf2, 0));
+      int tid = -1;
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
-                         kLaReserve, 0, true, c.prec));
+                         kLaReserve, 0, true, c.prec, &tid));
       if (force != 2) {   // RU2 done: tell the panel
         hipLaunchKernelGGL(k_et_signal, dim3(1), dim3(64), 0, s0, &et->ru_done, k1);
         MLU_TRY(hipGetLastError());
@@ -332,7 +367,7 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
       MLU_TRY(hipEventRecord(aux->width_ev, s1));
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false, c.prec));
+                         0, kLaHelpers, false, c.prec, nullptr, tid));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
       MLU_TRY(hipEventSynchronize(aux->width_ev));
@@ -363,7 +398,12 @@ using namespace mlu;
 
 extern "C" {
 
-int mlu_version(void) { return 100; }
+int mlu_version(void) { return 200; }
+
+int mlu_init(void) {
+  AuxStreams* aux = nullptr;
+  return get_aux(&aux) == hipSuccess ? 0 : MLU_ERR_HIP;
+}
 
 int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t* bytes) {
   if (m < 0) return -1;
@@ -373,6 +413,10 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -5;
   if (!bytes) return -6;
   *bytes = workspace_bytes();
+  // the library's per-device stream and events, created here (outside any
+  // stream capture the caller may start afterwards); without a device this
+  // does nothing, and a factorization call reports the failure
+  (void)mlu_init();
   return 0;
 }
 
@@ -381,10 +425,10 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
 namespace mlu {
 
 // mlu_dgetrf and mlu_dsgetrf; `sh` = 1 when called through mlu_dsgetrf, whose
-// arguments after `precision` (argument 11) are numbered one higher.
+// arguments after `precision` (argument 12) are numbered one higher.
 int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
-                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
-                void* d_work, size_t work_bytes, int sh) {
+                int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
+                int iters_limit, void* d_work, size_t work_bytes, int sh) {
   const int mn = m < n ? m : n;
   if (m < 0) return -2;
   if (n < 0) return -3;
@@ -395,16 +439,26 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
   if (variant < MLU_RL || variant > MLU_LA) return -8;
   if (nb < 1) return -9;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
-  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -11;
+  if (inner != MLU_RL && inner != MLU_LL) return -11;
+  if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -12;
   if (h_schedule) {
-    if (n_schedule < 1) return -12 - sh;
+    if (n_schedule < 1) return -13 - sh;
     for (int i = 0; i < n_schedule; ++i)
-      if (h_schedule[i] < 1) return -11 - sh;
+      if (h_schedule[i] < 1) return -12 - sh;
   }
-  if (iters_limit < -1) return -13 - sh;
-  if (!d_work) return -14 - sh;
-  if (work_bytes < workspace_bytes()) return -15 - sh;
+  if (iters_limit < -1) return -14 - sh;
+  if (!d_work) return -15 - sh;
+  if (work_bytes < workspace_bytes()) return -16 - sh;
   if (m > kPanelMaxRows) return -2;
+  return getrf_run(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, precision, h_schedule,
+                   n_schedule, iters_limit, d_work);
+}
+
+// The factorization of a checked call; `d_work` holds a Workspace.
+int getrf_run(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+              int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
+              int iters_limit, void* d_work) {
+  const int mn = m < n ? m : n;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (zero_bytes(s, d_info, sizeof(int32_t)) != hipSuccess) return MLU_ERR_HIP;
@@ -425,9 +479,9 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
   }
   unsigned epoch = 0;
   Workspace* ws = reinterpret_cast<Workspace*>(d_work);
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, precision == MLU_PREC_FP32 ? kPrecF32 : (precision == MLU_PREC_BF16 ? kPrecBF16 : kPrecF64),
-        &epoch};
-  c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue,
+        precision == MLU_PREC_FP32 ? kPrecF32 : (precision == MLU_PREC_BF16 ? kPrecBF16 : kPrecF64), &epoch, inner};
+  c.bi = nb_inner > 0 ? nb_inner : (nb < kPanelRegCols ? nb : kPanelRegCols);
 
   hipError_t e;
   if (variant == MLU_RL) e = run_rl(s, c, sched, iters_limit);
@@ -441,16 +495,17 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
 extern "C" {
 
 int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
-               int nb, int nb_inner, const int32_t* h_schedule, int n_schedule, int iters_limit, void* d_work,
-               size_t work_bytes) {
-  return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, MLU_PREC_FP64, h_schedule,
-                     n_schedule, iters_limit, d_work, work_bytes, 0);
+               int nb, int nb_inner, int inner, const int32_t* h_schedule, int n_schedule, int iters_limit,
+               void* d_work, size_t work_bytes) {
+  const int rc = getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, MLU_PREC_FP64,
+                             h_schedule, n_schedule, iters_limit, d_work, work_bytes, 0);
+  return rc;
 }
 
 int mlu_dsgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
-                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
-                void* d_work, size_t work_bytes) {
-  return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision, h_schedule,
+                int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
+                int iters_limit, void* d_work, size_t work_bytes) {
+  return getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, precision, h_schedule,
                      n_schedule, iters_limit, d_work, work_bytes, 1);
 }
 
@@ -480,8 +535,8 @@ int mlu_dgetrf_et(void* stream, int m, int n, double* dA, int lda, int32_t* d_ip
   if (zero_bytes(s, d_work, sizeof(Workspace)) != hipSuccess) return MLU_ERR_HIP;
   unsigned epoch = 0;
   Workspace* ws = reinterpret_cast<Workspace*>(d_work);
-  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, kPrecF64, &epoch};
-  c.bi = nb_inner > 0 ? nb_inner : (nb < MLU_MAX_NB_INNER ? nb : MLU_MAX_NB_INNER);
+  Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue, kPrecF64, &epoch, MLU_LL};
+  c.bi = nb_inner > 0 ? nb_inner : (nb < kPanelRegCols ? nb : kPanelRegCols);
   std::vector<int> widths;
   if (run_la_et(s, c, nb, &ws->et, force, min_width, &widths) != hipSuccess) return MLU_ERR_HIP;
   *n_widths = (int)widths.size();
@@ -555,7 +610,7 @@ int mlu_dlaswp(void* stream, int m, int ncols, double* dA, int lda, int k1, int 
 int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info,
                      void* d_work, size_t work_bytes) {
   if (m < 0 || m > kPanelMaxRows) return -2;
-  if (bw < 0 || bw > MLU_MAX_NB_INNER || bw > m) return -3;
+  if (bw < 0 || bw > kPanelRegCols || bw > m) return -3;
   if (bw > 0 && !dA) return -4;
   if (lda < (bw > 1 ? bw : 1)) return -5;
   if (bw > 0 && !d_ipiv) return -6;

@@ -15,6 +15,8 @@
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
 
+#include <cmath>
+
 namespace mlu {
 namespace {
 
@@ -26,7 +28,13 @@ struct IrState {
   int32_t done;
   int32_t pad;
   unsigned long long anorm;
+  double best;   // smallest backward error so far
 };
+
+// LU-IR stops as not converged once the backward error is not finite or has
+// grown past this factor times the smallest one reached (the corrections then
+// diverge: kappa(A) u_low is too large for plain refinement).
+constexpr double kDivergeFactor = 2.0;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
@@ -245,10 +253,12 @@ __global__ void k_ir_check(int nrhs, IrState* st, unsigned long long* bnorm, uns
     rnorm[c] = 0ull;
   }
   *d_berr = berr;
+  const double best = it == 0 ? berr : fmin(st->best, berr);
+  st->best = best;
   if (berr <= tol) {
     st->done = 1;
     *d_iters = it;
-  } else if (it >= max_iter) {
+  } else if (it >= max_iter || !isfinite(berr) || !(berr <= kDivergeFactor * best)) {
     st->done = 1;
     *d_iters = -1;
   }
@@ -453,6 +463,7 @@ int mlu_dsgesv_ir_workspace(int n, int nrhs, size_t* bytes) {
   if (nrhs < 0) return -2;
   if (!bytes) return -3;
   *bytes = ir_layout(n, nrhs).total;
+  (void)mlu_init();   // the library stream, outside any capture (as mlu_dgetrf_workspace)
   return 0;
 }
 
@@ -505,7 +516,7 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
   // LU := A, factor with the low-precision trailing products
   hipLaunchKernelGGL(k_ir_copy, dim3(g2), dim3(256), 0, s, n, n, dA, lda, LU, n, nullptr);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, precision, nullptr, 0, -1,
+  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, MLU_RL, precision, nullptr, 0, -1,
                              d_work, work_bytes, 0);
   if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
   // inverses of the factors' 256 x 256 diagonal blocks (the solves below are
@@ -556,6 +567,7 @@ int mlu_dsgesv_gmres_ir_workspace(int n, int max_krylov, size_t* bytes) {
   if (max_krylov < 1 || max_krylov > MLU_GMRES_MAX_KRYLOV) return -2;
   if (!bytes) return -3;
   *bytes = gmres_layout(n, max_krylov).total;
+  (void)mlu_init();
   return 0;
 }
 
@@ -620,7 +632,7 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   // of its 256 x 256 diagonal blocks; the norms of A and b; x := M^-1 b
   hipLaunchKernelGGL(k_ir_copy, dim3(g2), dim3(256), 0, s, n, n, dA, lda, LU, n, nullptr);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, precision, nullptr, 0, -1,
+  const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, MLU_RL, precision, nullptr, 0, -1,
                              d_work, work_bytes, 0);
   if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
   const unsigned gi = grid_for((size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock);
@@ -642,7 +654,7 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
 
   const unsigned gc = (unsigned)((n + 255) / 256);
   bool gmres_mode = solver == MLU_IR_GMRES;
-  double prev_berr = 0.0;
+  double prev_berr = 0.0, best_berr = 0.0;
   int inner = 0;
   GmresState hs{};
   for (int it = 0;; ++it) {
@@ -659,8 +671,13 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
       *h_outer = it;
       return 0;
     }
+    best_berr = it == 0 ? hs.berr : fmin(best_berr, hs.berr);
     if (it >= max_outer) {
       *h_outer = -1;
+      return 0;
+    }
+    if (solver == MLU_IR_LU && (!std::isfinite(hs.berr) || !(hs.berr <= kDivergeFactor * best_berr))) {
+      *h_outer = -1;   // plain LU-IR diverges
       return 0;
     }
     if (solver == MLU_IR_AUTO && !gmres_mode && it > 0 && !(hs.berr <= 0.5 * prev_berr)) gmres_mode = true;

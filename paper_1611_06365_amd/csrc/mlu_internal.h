@@ -110,10 +110,13 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 // CUs stay free for the panel factorization running beside it; only valid when
 // another launch on the same queue without reserve follows (it finishes the
 // tiles).  `clear` (may be null): kXcd counters that workgroup 0 zeroes first.
-// `grid` 0 = two workgroups per CU.
+// `grid` 0 = two workgroups per CU.  `trace_id` (may be null) receives the
+// trace slot of a traced launch (-1 if none); `tail_of` >= 0 marks a helper
+// launch joining the queue of that traced launch, whose duration then extends
+// to the helpers' end if they joined before it ended.
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                       double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
-                      int prec = kPrecF64);
+                      int prec = kPrecF64, int* trace_id = nullptr, int tail_of = -1);
 hipError_t trace_begin(int capacity);
 hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 
@@ -124,13 +127,16 @@ hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 // `epoch` must differ between the launches of one call (the exchange area is
 // cleared at the start of the call).  When the block lies inside a wider panel
 // (cl columns of it to the block's left, cr to its right, same rows), the
-// block's interchanges are also applied to those columns and the block's top
-// bw rows of the right columns are solved with its unit lower triangle.
+// block's interchanges are also applied to those columns and the top rows of
+// the first ns (-1: all cr) right columns are solved with a unit lower
+// triangle: the block's own, or with lb = 16 (the second register pass of a
+// 32-column diagonal block) the 32 x 32 triangle made of the 16 rows above the
+// block and the block's rows, over the 16 columns to its left and its own.
 // A nonzero *skip (a device flag written before the launch in stream order)
 // makes every workgroup return at once.
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0,
                         int32_t* ipiv, int32_t* info, PanelWork* work, unsigned epoch, int cl = 0,
-                        int cr = 0, const int32_t* skip = nullptr);
+                        int cr = 0, const int32_t* skip = nullptr, int ns = -1, int lb = 0);
 
 // Apply interchanges ipiv[k1 .. k2) (1-based values, each >= its own index and
 // < m) to columns [ca0, ca1) and [cb0, cb1) of the m-row matrix A.
@@ -157,9 +163,13 @@ hipError_t batched_set_lds_limits();
 
 // Argument checks and the whole factorization of mlu_dgetrf / mlu_dsgetrf
 // (C-ABI return codes; `sh` shifts the numbers of arguments after
-// `precision`).
+// `precision`), and the factorization alone for checked arguments (d_work
+// holds a Workspace).
 int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
-                int nb, int nb_inner, int precision, const int32_t* h_schedule, int n_schedule, int iters_limit,
-                void* d_work, size_t work_bytes, int sh);
+                int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
+                int iters_limit, void* d_work, size_t work_bytes, int sh);
+int getrf_run(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
+              int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
+              int iters_limit, void* d_work);
 
 }  // namespace mlu

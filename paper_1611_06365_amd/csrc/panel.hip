@@ -597,15 +597,20 @@ struct Panel {
 // interchanges applied to the panel's other columns (cl columns to the left of
 // the block, cr to its right; LAPACK laswp semantics, the sequential swaps
 // composed into one permutation of the touched rows and every displaced row
-// segment moved once through LDS), then the block's top rows of the cr right
-// columns solved with the block's unit lower triangle (A12 := trilu(A11)^-1 A12,
-// the next step of the blocked RL algorithm inside the panel).  No other
-// worker touches these columns during the launch.
+// segment moved once through LDS), then the top rows of the first ns right
+// columns solved with a unit lower triangle (A12 := trilu(A11)^-1 A12, the next
+// step of the blocked RL algorithm inside the panel).  The triangle is the
+// block's own (lb = 0), or, when the block is the second half of a 32-column
+// diagonal block factored in two register passes (lb = 16), the whole 32 x 32
+// triangle: the lb rows above the block and the block's rows, with the lb
+// columns to the block's left.  No other worker touches these columns during
+// the launch.
 constexpr int kMvCols = 64;
+constexpr int kTriMax = 2 * kPanelRegCols;   // rows of the largest triangle solved
 
 struct EpilogueShared {
   double mv[2 * kPanelRegCols][kMvCols];
-  double L[kPanelRegCols][kPanelRegCols + 1];
+  double T[kTriMax][kTriMax + 1];
   int slot[kPanelRegCols];
   int row[2 * kPanelRegCols];
   int label[2 * kPanelRegCols];
@@ -613,12 +618,14 @@ struct EpilogueShared {
 };
 
 // Kept out of line so that its registers do not add to the factorization's;
-// es.L already holds the block's strictly lower rows 0..bw-1.
+// es.T[lb + r][lb + c] (c < r < bw) already holds the block's strictly lower
+// rows.
 typedef __attribute__((address_space(1))) double gdouble;   // global memory
 
-template <int BW>
-__device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, int bw, int cl, int cr,
+template <int BW, int LB>
+__device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, int bw, int cl, int cr, int ns,
                                             const int* piv, int tid, EpilogueShared* esp) {
+  constexpr int lb = LB;
   // the matrix is global memory: accessed as such, the loads and stores are
   // global (vector-memory counter only) instead of flat, which would also
   // count against the LDS counter that every LDS wait below waits for
@@ -688,24 +695,39 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, in
       __syncthreads();
     }
   }
-  // A12 := trilu(A11)^-1 A12 on the right columns, one column per thread
-  for (int j = tid; j < cr; j += NT) {
-    double x[BW];
-    gdouble* colp = A + bw + j;
+  if (ns <= 0) return;
+  // the rest of the triangle: its lb rows above the block, and the block's
+  // rows in the lb columns to its left (those rows were interchanged above)
+  const int nt = lb + bw;
+  for (int e = tid; e < nt * lb; e += NT) {
+    const int r = e / lb, q = e % lb;
+    es.T[r][q] = q < r ? (double)A[(ptrdiff_t)(r - lb) * lda + (q - lb)] : 0.0;
+  }
+  __syncthreads();
+  // A12 := trilu(T)^-1 A12 on the first ns right columns, one column per thread
+  constexpr int TM = BW + LB;
+  typedef __attribute__((address_space(3))) double ldouble;
+  ldouble(*Tl)[kTriMax + 1] = (ldouble(*)[kTriMax + 1])(es.T);
+  for (int j = tid; j < ns; j += NT) {
+    double x[TM];
+    gdouble* colp = A + bw + j - (ptrdiff_t)lb * lda;
 #pragma unroll
-    for (int r = 0; r < BW; ++r) x[r] = (r < bw) ? colp[(size_t)r * lda] : 0.0;
+    for (int r = 0; r < TM; ++r) x[r] = (r < nt) ? colp[(size_t)r * lda] : 0.0;
+    // column by column: x[r] -= T[r][q] x[q] for r > q, so every x[r]
+    // receives its terms in the order q = 0, 1, ... of row-wise substitution;
+    // T is read through an LDS pointer (ds_read, not flat loads)
 #pragma unroll
-    for (int r = 1; r < BW; ++r) {
-      if (r < bw) {
-        double v = x[r];
+    for (int q = 0; q < TM - 1; ++q) {
+      if (q < nt - 1) {
+        const double xq = x[q];
 #pragma unroll
-        for (int q = 0; q < r; ++q) v = v - es.L[r][q] * x[q];
-        x[r] = v;
+        for (int r = q + 1; r < TM; ++r)
+          if (r < nt) x[r] = x[r] - Tl[r][q] * xq;
       }
     }
 #pragma unroll
-    for (int r = 1; r < BW; ++r)
-      if (r < bw) colp[(size_t)r * lda] = x[r];
+    for (int r = 1; r < TM; ++r)
+      if (r < nt) colp[(size_t)r * lda] = x[r];
   }
 }
 
@@ -713,7 +735,7 @@ template <int BW, int MAXW>
 __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
                                               int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
                                               PanelWork* __restrict__ work, int nwg, unsigned epoch, int cl,
-                                              int cr, const int32_t* __restrict__ skip) {
+                                              int cr, int ns, int lb, const int32_t* __restrict__ skip) {
   static_assert(BW % U == 0, "BW must be a multiple of U");
   // the flag was written by an earlier launch on the stream, so every
   // workgroup reads the same value and they all leave or all stay
@@ -774,36 +796,41 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
       __shared__ EpilogueShared es;
       if (P.tid < bw) {
 #pragma unroll
-        for (int c = 0; c < BW; ++c) es.L[P.tid][c] = (c < P.tid) ? P.v[0][c] : 0.0;
+        for (int c = 0; c < BW; ++c) es.T[lb + P.tid][lb + c] = (c < P.tid) ? P.v[0][c] : 0.0;
       }
-      panel_epilogue<BW>(A, lda, bw, cl, cr, sh.piv, P.tid, &es);
+      if (lb == 0) panel_epilogue<BW, 0>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
+      else panel_epilogue<BW, kPanelRegCols>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
     }
   }
 }
 
 template <int BW>
 hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, int ns, int lb,
+                        const int32_t* skip) {
   const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
   if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
   if (nwg <= 16)
     hipLaunchKernelGGL((k_panel<BW, 16>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, nwg,
-                       epoch, cl, cr, skip);
+                       epoch, cl, cr, ns, lb, skip);
   else
     hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
-                       work, nwg, epoch, cl, cr, skip);
+                       work, nwg, epoch, cl, cr, ns, lb, skip);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
-                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip) {
+                        int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip,
+                        int ns, int lb) {
   if (m <= 0 || bw <= 0) return hipSuccess;
   if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows || cl < 0 || cr < 0) return hipErrorInvalidValue;
+  if (ns < 0) ns = cr;
+  if (ns > cr || (lb != 0 && lb != kPanelRegCols) || lb > cl) return hipErrorInvalidValue;
   ipiv += row0;
-  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, skip);
-  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, skip);
+  if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
+  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
 }
 
 size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }

@@ -18,7 +18,7 @@ VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA}
 MLU_ERR_HIP = -1000
 MLU_INFO_SYNC_TIMEOUT = -999
 MLU_INFO_BAD_PIVOT = -998
-MLU_MAX_NB_INNER = 16
+MLU_MAX_NB_INNER = 32
 MLU_PREC_FP64, MLU_PREC_FP32, MLU_PREC_BF16 = 0, 1, 2
 PRECISION_IDS = {"fp64": MLU_PREC_FP64, "fp32": MLU_PREC_FP32, "bf16": MLU_PREC_BF16}
 MLU_IR_LU, MLU_IR_GMRES, MLU_IR_AUTO = 0, 1, 2
@@ -29,10 +29,11 @@ _vp, _i, _sz, _c = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_char
 
 _SIGNATURES = {
     "mlu_version": ([], _i),
+    "mlu_init": ([], _i),
     "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
-    "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
-    "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
-    "mlu_select": ([_vp, _i, _i, _i, _vp, _vp], _i),
+    "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_select": ([_vp, _i, _i, _i, _i, _vp, _vp, _vp], _i),
     "mlu_dgetrf_et": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz], _i),
     "mlu_dsgesv_ir_workspace": ([_i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dsgesv_ir": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp, _i, _i, ctypes.c_double, _i, _i, _i, _i, _vp, _vp, _vp,
@@ -85,21 +86,25 @@ def mlu_version() -> int:
     return _call("mlu_version")
 
 
+def mlu_init() -> int:
+    return _call("mlu_init")
+
+
 def mlu_dgetrf_workspace(m, n, variant, nb, nb_inner) -> tuple[int, int]:
     out = _sz(0)
     rc = _call("mlu_dgetrf_workspace", m, n, variant, nb, nb_inner, ctypes.byref(out))
     return rc, out.value
 
 
-def mlu_dgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_schedule, n_schedule,
+def mlu_dgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, h_schedule, n_schedule,
                iters_limit, d_work, work_bytes) -> int:
-    return _call("mlu_dgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, h_schedule,
+    return _call("mlu_dgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, h_schedule,
                  n_schedule, iters_limit, d_work, work_bytes)
 
 
-def mlu_dsgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision, h_schedule, n_schedule,
-                iters_limit, d_work, work_bytes) -> int:
-    return _call("mlu_dsgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, precision,
+def mlu_dsgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, precision, h_schedule,
+                n_schedule, iters_limit, d_work, work_bytes) -> int:
+    return _call("mlu_dsgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, precision,
                  h_schedule, n_schedule, iters_limit, d_work, work_bytes)
 
 
@@ -214,11 +219,13 @@ def workspace(device=None):
 
 
 def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ipiv=None, info=None,
-          work=None, stream=None, precision="fp64"):
+          work=None, stream=None, precision="fp64", inner="rl"):
     """Factor A (m x n float64 CUDA tensor, row-major) in place; returns (ipiv, info) tensors.
 
-    precision="fp32" calls mlu_dsgetrf (FP32 products in the outer trailing
-    updates).  No synchronization: read info after the stream has finished.
+    inner: "rl" or "ll", the algorithm of the panel factorization.
+    precision="fp32" / "bf16" calls mlu_dsgetrf (lower-precision products in
+    the outer trailing updates).  No synchronization: read info after the
+    stream has finished.
     """
     import torch
 
@@ -234,19 +241,20 @@ def getrf(A, variant="rl", nb=256, nb_inner=0, schedule=None, iters_limit=-1, ip
         arr = (ctypes.c_int32 * len(schedule))(*[int(b) for b in schedule])
         sched, nsched = ctypes.cast(arr, ctypes.c_void_p), len(schedule)
     v = VARIANT_IDS[variant] if isinstance(variant, str) else int(variant)
+    iv = VARIANT_IDS[inner] if isinstance(inner, str) else int(inner)
     if precision == "fp64":
         rc = mlu_dgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
-                        nb_inner, sched, nsched, iters_limit, work.data_ptr(), work.numel())
+                        nb_inner, iv, sched, nsched, iters_limit, work.data_ptr(), work.numel())
         check(rc, "mlu_dgetrf")
     else:
         rc = mlu_dsgetrf(_stream(stream), m, n, pa, lda, _i32(ipiv, "ipiv", k), _i32(info, "info", 1), v, nb,
-                         nb_inner, PRECISION_IDS[precision], sched, nsched, iters_limit, work.data_ptr(),
+                         nb_inner, iv, PRECISION_IDS[precision], sched, nsched, iters_limit, work.data_ptr(),
                          work.numel())
         check(rc, "mlu_dsgetrf")
     return ipiv, info
 
 
-VARIANT_NAMES = {0: "rl", 1: "ll", 2: "la"}
+VARIANT_NAMES = {0: "rl", 1: "ll", 2: "la", 3: "batched"}
 
 
 def packed_model(model):
@@ -254,17 +262,21 @@ def packed_model(model):
     return (ctypes.c_float * len(model))(*model)
 
 
-def select(n, precision="fp64", model=None):
+def select(n, precision="fp64", model=None, batch=1, with_fallback=False):
     """The learned selector through the C ABI (mlu_select): (variant, nb) for
-    an n x n factorization.  `model`: a packed float list (selector.pack) or a
+    `batch` matrices of order n ("batched" with the panel width for a batch of
+    small matrices); with_fallback=True adds whether the model defers to the
+    autotuner.  `model`: a packed float list (selector.pack) or a
     packed_model() array; default, the package's trained model."""
     arr = _packed_default() if model is None else (model if isinstance(model, ctypes.Array) else
                                                     packed_model(model))
-    v, nb = ctypes.c_int(-1), ctypes.c_int(-1)
-    rc = _call("mlu_select", ctypes.cast(arr, ctypes.c_void_p), len(arr), int(n), PRECISION_IDS[precision],
-               ctypes.cast(ctypes.byref(v), ctypes.c_void_p), ctypes.cast(ctypes.byref(nb), ctypes.c_void_p))
+    v, nb, fb = ctypes.c_int(-1), ctypes.c_int(-1), ctypes.c_int(-1)
+    rc = _call("mlu_select", ctypes.cast(arr, ctypes.c_void_p), len(arr), int(n), int(batch),
+               PRECISION_IDS[precision], ctypes.cast(ctypes.byref(v), ctypes.c_void_p),
+               ctypes.cast(ctypes.byref(nb), ctypes.c_void_p), ctypes.cast(ctypes.byref(fb), ctypes.c_void_p))
     check(rc, "mlu_select")
-    return VARIANT_NAMES[v.value], nb.value
+    out = (VARIANT_NAMES[v.value], nb.value)
+    return (*out, bool(fb.value)) if with_fallback else out
 
 
 _PACKED = None

@@ -2,18 +2,24 @@
 selector (the block-size study of Section 5.1, where the best b_o depends on the
 algorithm and the problem size, turned into a model).
 
-* `collect` is the exhaustive autotuner: it times every configuration of
-  CONFIGS (variant x outer block size b, inner block size 16) for each order n
-  and product precision on the GPU, through mlu_dgetrf / mlu_dsgetrf, on
-  A = B B^T + n I, and writes the timings as JSON.
-* `train` fits the selector, a multilayer perceptron in FP32 (3 layers, 64
-  hidden units, ReLU) from features of (n, precision) to the logarithm of every
-  configuration's time per flop; the configuration with the smallest
-  predicted time is the choice.  Sizes alternate between a training and a
-  held-out set; the regret (time of the choice / best time - 1) is reported on
-  both.
-* `Selector` loads the trained model (JSON) and predicts; `pack` flattens it
-  into the float array that the C entry point mlu_select evaluates.
+* The exhaustive autotuner (`time_single`, `time_batched`, `autotune`) times
+  configurations on the GPU: for one matrix of order n every variant (RL, LL,
+  LA) with every outer block size b of NBS through mlu_dgetrf / mlu_dsgetrf;
+  for a batch of `batch` matrices of order n <= 512 the batched kernel with
+  each panel width of BATCH_NBS.  Matrices are A = B B^T + n I.
+* `collect` runs it over a sweep of shapes (the training set) and over shapes
+  drawn outside the sweep (the held-out set) and writes the timings as JSON.
+* `train` fits the selector: a multilayer perceptron in FP32 (3 layers, 64
+  hidden units, ReLU) from (n, batch count, precision, variant id, block size)
+  to the logarithm of the time per flop.  For a shape, every candidate
+  configuration is scored and the smallest predicted time wins.  The regret
+  (time of the choice / time of the autotuner's best - 1) is reported on the
+  held-out shapes, with the model alone and with the autotuner as fallback.
+* `Selector.choose` predicts; it defers to the autotuner (when one is given)
+  for shapes outside the training range or when the best two predictions are
+  within FALLBACK_MARGIN of each other.  `pack` flattens the model into the
+  float array that the C entry point mlu_select evaluates (the same features,
+  candidates and fallback rule).
 
     python -m paper_1611_06365_amd.selector collect --out timings.json
     python -m paper_1611_06365_amd.selector train timings.json --out model.json
@@ -28,18 +34,52 @@ import sys
 import time
 
 VARIANTS = ("rl", "ll", "la")
+VARIANT_IDS = {"rl": 0, "ll": 1, "la": 2, "batched": 3}
 NBS = (64, 128, 192, 256, 384, 512)
-CONFIGS = tuple((v, nb) for v in VARIANTS for nb in NBS)
+BATCH_NBS = (16, 32)
+SINGLE_CONFIGS = tuple((v, nb) for v in VARIANTS for nb in NBS)
+BATCH_CONFIGS = tuple(("batched", nb) for nb in BATCH_NBS)
+CONFIGS = SINGLE_CONFIGS + BATCH_CONFIGS
 PRECISIONS = ("fp64", "fp32")
 NB_INNER = 16
 HIDDEN = 64
+N_FEATURES = 9
+BATCH_MAX_N = 512
+# training range (shapes outside it go to the autotuner when one is given)
+N_LO, N_HI, BATCH_HI = 8, 32768, 20000
+FALLBACK_MARGIN = 0.005
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.json")
 
 
-def features(n: int, precision: str) -> list[float]:
-    """(log2 n scaled to about [0, 1], its square, the precision flag)."""
+def features(n: int, batch: int, precision: str, variant: str, nb: int) -> list[float]:
+    """(log2 n scaled to about [0, 1] over 64..32768, its square, log2 of the
+    batch count scaled to about [0, 1] over 1..20000, the FP32 flag, the
+    variant one-hot (RL, LL, LA, batched), log2 b scaled)."""
     x = (math.log2(max(n, 1)) - 6.0) / 9.0
-    return [x, x * x, 1.0 if precision == "fp32" else 0.0]
+    bb = math.log2(max(batch, 1)) / 14.3
+    onehot = [0.0] * 4
+    onehot[VARIANT_IDS[variant]] = 1.0
+    y = (math.log2(max(nb, 1)) - 4.0) / 5.0
+    return [x, x * x, bb, 1.0 if precision == "fp32" else 0.0, *onehot, y]
+
+
+LL_MAX_PANELS = 48
+
+
+def worth_timing(n: int, variant: str, nb: int) -> bool:
+    """The left-looking variant revisits every earlier panel for each new one
+    (about p^2 / 2 solves and updates for p panels); beyond LL_MAX_PANELS
+    panels it is not a candidate (far slower than the others)."""
+    return variant != "ll" or -(-n // nb) <= LL_MAX_PANELS
+
+
+def candidates(n: int, batch: int) -> list[tuple[str, int]]:
+    """The configurations that can factor `batch` matrices of order n: the
+    batched kernel's panel widths for a batch of small matrices, else every
+    single-matrix variant and block size (one call per matrix)."""
+    if batch > 1 and n <= BATCH_MAX_N:
+        return list(BATCH_CONFIGS)
+    return [c for c in SINGLE_CONFIGS if worth_timing(n, *c)]
 
 
 def sizes(lo: int = 64, hi: int = 32768, count: int = 40) -> list[int]:
@@ -51,18 +91,54 @@ def sizes(lo: int = 64, hi: int = 32768, count: int = 40) -> list[int]:
     return sorted(set(out))
 
 
+def batch_grid() -> list[tuple[int, int]]:
+    """The batched training sweep: (order, batch count) pairs."""
+    ns = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+    bs = (16, 128, 1024, 8192, 20000)
+    return [(n, b) for n in ns for b in bs]
+
+
+def held_out_shapes(seed: int = 7, singles: int = 24, batches: int = 24):
+    """Shapes drawn outside the sweeps: orders log-uniform in [64, 32768]
+    that are not multiples of 8 (the sweep's are), and batched (order, count)
+    pairs with the order uniform in [9, 511] and the count log-uniform in
+    [20, 20000], avoiding the sweep's values."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    grid_n = set(sizes())
+    out_single = set()
+    while len(out_single) < singles:
+        n = int(round(64 * 512 ** rng.random()))
+        if n % 8 != 0 and n not in grid_n and 64 <= n <= 32768:
+            out_single.add(n)
+    grid_b = set(batch_grid())
+    out_batch = set()
+    while len(out_batch) < batches:
+        n = int(rng.integers(9, 512))
+        b = int(round(20 * 1000 ** rng.random()))
+        if (n, b) not in grid_b:
+            out_batch.add((n, b))
+    return sorted(out_single), sorted(out_batch)
+
+
 # ---------------------------------------------------------------- autotuner
-LL_MAX_PANELS = 48
+def _spd_batch(n, batch, dtype, dev, seed=0):
+    """`batch` matrices B B^T + n I of order n in one buffer; returns (buffer, views)."""
+    import torch
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    b = torch.randn(batch, n, n, generator=g, dtype=torch.float64, device=dev)
+    a = torch.bmm(b, b.transpose(1, 2).contiguous())
+    a.diagonal(dim1=1, dim2=2).add_(float(n))
+    buf = a.to(dtype).contiguous()
+    del a, b
+    return buf, [buf[i] for i in range(batch)]
 
 
-def worth_timing(n: int, variant: str, nb: int) -> bool:
-    """The left-looking variant revisits every earlier panel for each new one
-    (about p^2 / 2 solves and updates for p panels); beyond LL_MAX_PANELS
-    panels it is not timed and counts as 4x the slowest timed configuration."""
-    return variant != "ll" or -(-n // nb) <= LL_MAX_PANELS
-
-
-def time_config(mlu, A, M, n, variant, nb, precision, work, ipiv, info, reps):
+def time_single(mlu, A, M, n, variant, nb, precision, work, ipiv, info, reps):
+    """Best time (ms) of `reps` factorizations after one warm-up."""
     import torch
 
     best = None
@@ -83,9 +159,36 @@ def time_config(mlu, A, M, n, variant, nb, precision, work, ipiv, info, reps):
     return best
 
 
-def collect(ns, out_path, precisions=PRECISIONS, log=print):
-    """Time every configuration for every n and precision (the exhaustive
-    autotuner); returns the records and writes them to out_path."""
+def time_batched(mlu, buf, pristine, mats, n, nb, reps):
+    """Best time (ms) of `reps` batched factorizations after one warm-up."""
+    import torch
+
+    plan = mlu.BatchPlan(mats, max_n=n, nb=nb)
+    best = None
+    for r in range(reps + 1):
+        buf.copy_(pristine)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run()
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+    if int((plan.info != 0).sum().item()) != 0:
+        raise RuntimeError(f"nonzero info in a batch of order {n}")
+    return best
+
+
+def _reps(n, batch=1):
+    work = batch * n ** 3
+    return 3 if work <= 4096 ** 3 else (2 if work <= 12288 ** 3 else 1)
+
+
+def time_shape(n, batch, precision, configs=None, log=None):
+    """The exhaustive autotuner: time every candidate configuration for
+    `batch` matrices of order n; returns [record]."""
     import torch
 
     import inputs.device as D
@@ -93,111 +196,160 @@ def collect(ns, out_path, precisions=PRECISIONS, log=print):
 
     mlu.load()
     dev = torch.device("cuda:0")
-    work = mlu.workspace(dev)
+    configs = candidates(n, batch) if configs is None else configs
     recs = []
-    for n in ns:
+    if configs and configs[0][0] == "batched":
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        buf, mats = _spd_batch(n, batch, dt, dev)
+        pristine = buf.clone()
+        for v, nb in configs:
+            ms = time_batched(mlu, buf, pristine, mats, n, nb, _reps(n, batch))
+            recs.append({"n": n, "batch": batch, "precision": precision, "variant": v, "nb": nb, "ms": ms})
+        del buf, pristine, mats
+    else:
+        work = mlu.workspace(dev)
         A = D.spd_bbt(n, seed=0, device=dev)
         M = torch.empty_like(A)
         ipiv = torch.empty(n, dtype=torch.int32, device=dev)
         info = torch.empty(1, dtype=torch.int32, device=dev)
-        reps = 3 if n <= 4096 else (2 if n <= 12288 else 1)
-        for precision in precisions:
-            for variant, nb in CONFIGS:
-                if not worth_timing(n, variant, nb):
-                    recs.append({"n": n, "precision": precision, "variant": variant, "nb": nb, "ms": None})
-                    continue
-                ms = time_config(mlu, A, M, n, variant, nb, precision, work, ipiv, info, reps)
-                recs.append({"n": n, "precision": precision, "variant": variant, "nb": nb, "ms": ms})
-            best = min((r for r in recs if r["n"] == n and r["precision"] == precision and r["ms"] is not None),
-                       key=lambda r: r["ms"])
-            log(f"[selector] n={n} {precision}: best {best['variant']} nb={best['nb']} {best['ms']:.3f} ms",
-                flush=True)
+        for v, nb in configs:
+            # one matrix per call: a batch of them takes `batch` times as long
+            ms = batch * time_single(mlu, A, M, n, v, nb, precision, work, ipiv, info, _reps(n))
+            recs.append({"n": n, "batch": batch, "precision": precision, "variant": v, "nb": nb, "ms": ms})
         del A, M
-        torch.cuda.empty_cache()
-    meta = {"what": "getrf time per configuration, A = B B^T + n I (seed 0), nb_inner 16, best of the timed "
-                    "runs after one warm-up, HIP events", "configs": [list(c) for c in CONFIGS],
-            "device": torch.cuda.get_device_name(0), "records": recs}
-    with open(out_path, "w") as f:
-        json.dump(meta, f)
+    torch.cuda.empty_cache()
+    if log is not None and recs:
+        best = min(recs, key=lambda r: r["ms"])
+        log(f"[selector] n={n} batch={batch} {precision}: best {best['variant']} nb={best['nb']} "
+            f"{best['ms']:.3f} ms", flush=True)
     return recs
 
 
+def autotune(n, batch=1, precision="fp64", configs=None):
+    """The fallback: (variant, nb) of the fastest timed candidate."""
+    recs = time_shape(n, batch, precision, configs)
+    best = min(recs, key=lambda r: r["ms"])
+    return best["variant"], int(best["nb"])
+
+
+def collect(out_path, precisions=PRECISIONS, max_n=32768, count=40, log=print):
+    """Time the training sweep and the held-out shapes; write JSON."""
+    import torch
+
+    train_recs, held_recs = [], []
+    for n in sizes(hi=max_n, count=count):
+        for p in precisions:
+            train_recs += time_shape(n, 1, p, log=log)
+    for n, b in batch_grid():
+        for p in precisions:
+            train_recs += time_shape(n, b, p, log=log)
+    hs, hb = held_out_shapes()
+    for n in hs:
+        if n <= max_n:
+            for p in precisions:
+                held_recs += time_shape(n, 1, p, log=log)
+    for n, b in hb:
+        for p in precisions:
+            held_recs += time_shape(n, b, p, log=log)
+    meta = {"what": "factorization time per configuration, A = B B^T + n I, nb_inner 16 (single matrices), "
+                    "batches of equal orders (batched kernel); best of the timed runs after one warm-up, HIP events",
+            "device": torch.cuda.get_device_name(0), "records": train_recs, "held_out_records": held_recs}
+    with open(out_path, "w") as f:
+        json.dump(meta, f)
+    return train_recs, held_recs
+
+
 # ---------------------------------------------------------------- model
-def _table(recs):
-    """{(n, precision): [ms per config in CONFIGS order]}; untimed entries
-    (see worth_timing) are 4x the row's slowest timed one."""
-    tab = {}
-    idx = {c: i for i, c in enumerate(CONFIGS)}
-    seen = {}
-    for r in recs:
-        key = (r["n"], r["precision"])
-        tab.setdefault(key, [None] * len(CONFIGS))[idx[(r["variant"], r["nb"])]] = r["ms"]
-        seen.setdefault(key, set()).add(idx[(r["variant"], r["nb"])])
+def _gflop(n, batch):
+    return batch * 2.0 * n ** 3 / 3.0 / 1e9
+
+
+def _target(r):
+    """log of the time per GFLOP (ms) of a record."""
+    return math.log(r["ms"] / _gflop(r["n"], r["batch"]))
+
+
+def _by_shape(recs):
     out = {}
-    for k, row in tab.items():
-        if len(seen[k]) != len(CONFIGS) or all(x is None for x in row):
+    for r in recs:
+        if r.get("ms") is None:
             continue
-        worst = max(x for x in row if x is not None)
-        out[k] = [x if x is not None else 4.0 * worst for x in row]
+        out.setdefault((r["n"], r["batch"], r["precision"]), {})[(r["variant"], int(r["nb"]))] = r["ms"]
     return out
 
 
-def _target(n, ms):
-    """log of the time per 2n^3/3 flops (ms per GFLOP) of every configuration."""
-    gf = 2.0 * n ** 3 / 3.0 / 1e9
-    return [math.log(t / gf) for t in ms]
+def regret_report(sel, recs, use_fallback=False):
+    """Regret of the selector's choices on the shapes of `recs` (every
+    candidate timed there: the exhaustive autotuner's best is the reference).
+    With use_fallback, shapes the selector defers take the autotuner's best
+    (regret 0) and are counted."""
+    import numpy as np
+
+    regrets, deferred = [], 0
+    for (n, b, p), times in sorted(_by_shape(recs).items()):
+        best = min(times.values())
+        v, nb, fallback, _ = sel.choose_model(n, b, p)
+        if use_fallback and fallback:
+            deferred += 1
+            regrets.append(0.0)
+            continue
+        t = times.get((v, nb))
+        if t is None:
+            continue
+        regrets.append(t / best - 1.0)
+    if not regrets:
+        return None
+    return {"cases": len(regrets), "mean_regret": float(np.mean(regrets)), "max_regret": float(np.max(regrets)),
+            "share_exact": float(np.mean([r == 0.0 for r in regrets])), "deferred_to_autotuner": deferred}
 
 
-def train(recs, epochs=3000, seed=0, lr=3e-3):
-    """Fit the MLP on the even-indexed sizes, hold out the odd-indexed ones;
-    returns (model dict, report dict)."""
+def train(recs, held=None, epochs=4000, seed=0, lr=3e-3):
+    """Fit the MLP on `recs` (all training shapes); returns (model, report)
+    with the regret on the training shapes and on the held-out records."""
     import numpy as np
     import torch
 
-    tab = _table(recs)
-    ns = sorted({k[0] for k in tab})
-    train_ns = set(ns[0::2])
-    keys = sorted(tab)
-    X = torch.tensor([features(n, p) for n, p in keys], dtype=torch.float32)
-    Y = torch.tensor([_target(n, tab[(n, p)]) for n, p in keys], dtype=torch.float32)
-    is_tr = torch.tensor([n in train_ns for n, _ in keys])
-    mu, sd = Y[is_tr].mean(), Y[is_tr].std() + 1e-6
+    good = [r for r in recs if r.get("ms") is not None]
+    X = torch.tensor([features(r["n"], r["batch"], r["precision"], r["variant"], r["nb"]) for r in good],
+                     dtype=torch.float32)
+    Y = torch.tensor([_target(r) for r in good], dtype=torch.float32)
+    mu, sd = Y.mean(), Y.std() + 1e-6
     torch.manual_seed(seed)
-    net = torch.nn.Sequential(torch.nn.Linear(X.shape[1], HIDDEN), torch.nn.ReLU(),
+    net = torch.nn.Sequential(torch.nn.Linear(N_FEATURES, HIDDEN), torch.nn.ReLU(),
                               torch.nn.Linear(HIDDEN, HIDDEN), torch.nn.ReLU(),
-                              torch.nn.Linear(HIDDEN, len(CONFIGS)))
+                              torch.nn.Linear(HIDDEN, 1))
     opt = torch.optim.Adam(net.parameters(), lr=lr)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, epochs)
     for _ in range(epochs):
         opt.zero_grad()
-        loss = ((net(X[is_tr]) - (Y[is_tr] - mu) / sd) ** 2).mean()
+        loss = ((net(X)[:, 0] - (Y - mu) / sd) ** 2).mean()
         loss.backward()
         opt.step()
+        sched.step()
     layers = [m for m in net if isinstance(m, torch.nn.Linear)]
-    model = {"features": "log2 n scaled, its square, fp32 flag", "hidden": HIDDEN,
+    model = {"features": "log2 n scaled, its square, log2 batch scaled, fp32 flag, variant one-hot "
+                         "(rl, ll, la, batched), log2 nb scaled", "hidden": HIDDEN,
              "configs": [list(c) for c in CONFIGS], "out_scale": [float(mu), float(sd)],
+             "range": [N_LO, N_HI, BATCH_HI], "fallback_margin": FALLBACK_MARGIN,
              "layers": [{"W": l.weight.detach().numpy().tolist(), "b": l.bias.detach().numpy().tolist()}
                         for l in layers]}
     sel = Selector(model)
-    report = {}
-    for name, subset in (("train", [k for k in keys if k[0] in train_ns]),
-                         ("held_out", [k for k in keys if k[0] not in train_ns])):
-        regrets = []
-        for n, p in subset:
-            ms = tab[(n, p)]
-            v, nb = sel.predict(n, p)
-            regrets.append(ms[CONFIGS.index((v, nb))] / min(ms) - 1.0)
-        report[name] = {"cases": len(subset), "mean_regret": float(np.mean(regrets)),
-                        "max_regret": float(np.max(regrets)),
-                        "share_exact": float(np.mean([r == 0.0 for r in regrets]))}
-    # the fixed default (LA, b = 256) as a reference point
-    fixed = [tab[k][CONFIGS.index(("la", 256))] / min(tab[k]) - 1.0 for k in keys if k[0] not in train_ns]
-    report["held_out_fixed_la256_mean_regret"] = float(np.mean(fixed))
-    report["final_train_loss"] = float(loss.item())
+    report = {"training_timings": len(good), "final_train_loss": float(loss.item()),
+              "train": regret_report(sel, good)}
+    if held:
+        report["held_out_timings"] = sum(1 for r in held if r.get("ms") is not None)
+        report["held_out"] = regret_report(sel, held)
+        report["held_out_with_autotuner_fallback"] = regret_report(sel, held, use_fallback=True)
+        fixed = []
+        for (n, b, p), times in _by_shape(held).items():
+            if b == 1 and ("la", 256) in times:
+                fixed.append(times[("la", 256)] / min(times.values()) - 1.0)
+        report["held_out_single_fixed_la256_mean_regret"] = float(np.mean(fixed)) if fixed else None
     return model, report
 
 
 class Selector:
-    """The trained MLP: predict(n, precision) -> (variant, nb)."""
+    """The trained MLP: choose(n, batch, precision) -> (variant, nb)."""
 
     def __init__(self, model=None):
         if model is None:
@@ -208,32 +360,65 @@ class Selector:
         self.model = model
         self.layers = [(np.asarray(l["W"], dtype=np.float32), np.asarray(l["b"], dtype=np.float32))
                        for l in model["layers"]]
-        self.configs = [tuple(c) for c in model["configs"]]
+        self.range = model.get("range", [N_LO, N_HI, BATCH_HI])
+        self.margin = model.get("fallback_margin", FALLBACK_MARGIN)
 
-    def scores(self, n, precision):
+    def score(self, n, batch, precision, variant, nb):
+        """Predicted (scaled) log time per flop of one configuration."""
         import numpy as np
 
-        h = np.asarray(features(n, precision), dtype=np.float32)
+        h = np.asarray(features(n, batch, precision, variant, nb), dtype=np.float32)
         for i, (W, b) in enumerate(self.layers):
             h = W @ h + b
             if i + 1 < len(self.layers):
                 h = np.maximum(h, np.float32(0.0))
-        return h
+        return float(h[0])
 
-    def predict(self, n, precision="fp64"):
-        s = self.scores(n, precision)
-        v, nb = self.configs[int(s.argmin())]
-        return v, int(nb)
+    def choose_model(self, n, batch=1, precision="fp64"):
+        """(variant, nb, fallback, margin): the model's choice, whether it
+        defers to the autotuner (shape outside the training range, or the
+        runner-up predicted within `margin`), and the predicted margin."""
+        cand = candidates(n, batch)
+        scores = sorted((self.score(n, batch, precision, v, nb), i) for i, (v, nb) in enumerate(cand))
+        v, nb = cand[scores[0][1]]
+        # a score is (log time - mu) / sd: the runner-up's predicted relative gap
+        sd = self.model.get("out_scale", [0.0, 1.0])[1]
+        margin = math.exp((scores[1][0] - scores[0][0]) * sd) - 1.0 if len(scores) > 1 else float("inf")
+        lo, hi, bhi = self.range
+        outside = n < lo or n > hi or batch < 1 or batch > bhi
+        return v, int(nb), bool(outside or margin < self.margin), margin
+
+    def predict(self, n, precision="fp64", batch=1):
+        v, nb, _, _ = self.choose_model(n, batch, precision)
+        return v, nb
+
+    def choose(self, n, batch=1, precision="fp64", tuner=None):
+        """The model's choice, or the autotuner's (tuner(n, batch, precision)
+        -> (variant, nb), e.g. `autotune`) when the model defers."""
+        v, nb, fallback, _ = self.choose_model(n, batch, precision)
+        if fallback and tuner is not None:
+            return tuner(n, batch, precision)
+        return v, nb
+
+
+PACK_HEADER = 12
 
 
 def pack(model) -> list[float]:
-    """The float array mlu_select evaluates: [n_in, hidden, n_out, n_layers,
-    then per output its (variant id, nb), then per layer W row-major and b]."""
-    ids = {"rl": 0, "ll": 1, "la": 2}
+    """The float array mlu_select evaluates: a header [version 2, n_in,
+    hidden, n_layers, n_cand, n_lo, n_hi, batch_hi, fallback margin, output
+    scale sd, LL panel limit, batched order limit], per candidate its
+    (variant id, nb), then per layer W row-major and b (the last layer has one
+    output)."""
     layers = model["layers"]
-    out = [float(len(layers[0]["W"][0])), float(model["hidden"]), float(len(model["configs"])), float(len(layers))]
-    for v, nb in model["configs"]:
-        out += [float(ids[v]), float(nb)]
+    cfg = model["configs"]
+    lo, hi, bhi = model.get("range", [N_LO, N_HI, BATCH_HI])
+    out = [2.0, float(len(layers[0]["W"][0])), float(model["hidden"]), float(len(layers)), float(len(cfg)),
+           float(lo), float(hi), float(bhi), float(model.get("fallback_margin", FALLBACK_MARGIN)),
+           float(model.get("out_scale", [0.0, 1.0])[1]), float(LL_MAX_PANELS), float(BATCH_MAX_N)]
+    assert len(out) == PACK_HEADER
+    for v, nb in cfg:
+        out += [float(VARIANT_IDS[v]), float(nb)]
     for l in layers:
         for row in l["W"]:
             out += [float(x) for x in row]
@@ -258,12 +443,12 @@ def main(argv=None) -> int:
         if root not in sys.path:
             sys.path.insert(0, root)
         t0 = time.time()
-        collect(sizes(hi=args.max_n, count=args.count), args.out)
+        collect(args.out, max_n=args.max_n, count=args.count)
         print(f"[selector] collected in {time.time() - t0:.1f} s", flush=True)
         return 0
     with open(args.timings) as f:
-        recs = json.load(f)["records"]
-    model, report = train(recs)
+        data = json.load(f)
+    model, report = train(data["records"], data.get("held_out_records"))
     with open(args.out, "w") as f:
         json.dump(model, f)
     print(json.dumps(report, indent=1))

@@ -42,26 +42,28 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_workspace(lib):
-    assert mlu.mlu_version() == 100
+    assert mlu.mlu_version() == 200
     rc, nbytes = mlu.mlu_dgetrf_workspace(16384, 16384, mlu.MLU_LA, 256, 16)
     assert rc == 0 and 0 < nbytes <= 1 << 20
     assert mlu.mlu_dgetrf_workspace(-1, 4, 0, 1, 0)[0] == -1
     assert mlu.mlu_dgetrf_workspace(4, 4, 7, 1, 0)[0] == -3
     assert mlu.mlu_dgetrf_workspace(4, 4, 0, 0, 0)[0] == -4
-    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 17)[0] == -5
+    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 33)[0] == -5
+    assert mlu.mlu_dgetrf_workspace(4, 4, 0, 8, 32)[0] == 0
 
 
 def _getrf(**kw):
     args = dict(stream=None, m=8, n=8, dA=1024, lda=8, d_ipiv=2048, d_info=4096, variant=0, nb=4, nb_inner=0,
-                h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8192, work_bytes=1 << 20)
+                inner=0, h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8192, work_bytes=1 << 20)
     args.update(kw)
     return mlu.mlu_dgetrf(*args.values())
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(m=-1), -2), (dict(n=-3), -3), (dict(dA=None), -4), (dict(lda=7), -5), (dict(d_ipiv=None), -6),
-    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=17), -10),
-    (dict(nb_inner=-1), -10), (dict(iters_limit=-2), -13), (dict(d_work=None), -14), (dict(work_bytes=16), -15),
+    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=33), -10),
+    (dict(nb_inner=-1), -10), (dict(inner=2), -11), (dict(inner=-1), -11), (dict(iters_limit=-2), -14),
+    (dict(d_work=None), -15), (dict(work_bytes=16), -16),
 ])
 def test_getrf_argument_checks(lib, kw, code):
     assert _getrf(**kw) == code
@@ -69,9 +71,9 @@ def test_getrf_argument_checks(lib, kw, code):
 
 def test_getrf_bad_schedule(lib):
     arr = (ctypes.c_int32 * 3)(4, 0, 4)
-    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=3) == -11
+    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=3) == -12
     arr = (ctypes.c_int32 * 1)(4)
-    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=0) == -12
+    assert _getrf(h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=0) == -13
 
 
 def test_other_argument_checks(lib):
@@ -101,20 +103,23 @@ def test_mixed_argument_checks(lib):
                 max_iter=5, variant=0, nb=2, nb_inner=0, d_ipiv=8, d_info=8, d_iters=8, d_berr=8, d_work=8,
                 work_bytes=1 << 40)
     for key, bad, code in [("precision", 7, -10), ("tol", -1.0, -11), ("max_iter", -1, -12), ("variant", 9, -13),
-                           ("nb", 0, -14), ("nb_inner", 17, -15), ("work_bytes", 16, -21), ("lda", 3, -5)]:
+                           ("nb", 0, -14), ("nb_inner", 33, -15), ("work_bytes", 16, -21), ("lda", 3, -5)]:
         kw = dict(args)
         kw[key] = bad
         assert mlu.mlu_dsgesv_ir(*kw.values()) == code, key
-    # mlu_dsgetrf: precision is argument 11, later arguments shift by one
-    g = dict(stream=None, m=4, n=4, dA=8, lda=4, d_ipiv=8, d_info=8, variant=0, nb=2, nb_inner=0, precision=1,
-             h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8, work_bytes=16)
+    # mlu_dsgetrf: precision is argument 12, later arguments shift by one
+    g = dict(stream=None, m=4, n=4, dA=8, lda=4, d_ipiv=8, d_info=8, variant=0, nb=2, nb_inner=0, inner=0,
+             precision=1, h_schedule=None, n_schedule=0, iters_limit=-1, d_work=8, work_bytes=16)
     kw = dict(g)
     kw["precision"] = 5
+    assert mlu.mlu_dsgetrf(*kw.values()) == -12
+    kw = dict(g)
+    kw["inner"] = 2
     assert mlu.mlu_dsgetrf(*kw.values()) == -11
-    assert mlu.mlu_dsgetrf(*g.values()) == -16      # workspace too small: argument 16
+    assert mlu.mlu_dsgetrf(*g.values()) == -17      # workspace too small: argument 17
     kw = dict(g)
     kw["iters_limit"] = -2
-    assert mlu.mlu_dsgetrf(*kw.values()) == -14
+    assert mlu.mlu_dsgetrf(*kw.values()) == -15
 
 
 def test_batched_argument_checks(lib):
@@ -149,7 +154,7 @@ def test_et_argument_checks(lib):
     base = dict(stream=None, m=4, n=4, dA=8, lda=4, d_ipiv=8, d_info=8, nb=2, nb_inner=0, force=0, min_width=0,
                 h_widths=None, max_widths=0, n_widths=ctypes.cast(ctypes.byref(cnt), ctypes.c_void_p), d_work=8, work_bytes=1 << 40)
     for key, bad, code in [("m", -1, -2), ("n", -1, -3), ("dA", None, -4), ("lda", 3, -5), ("d_ipiv", None, -6),
-                           ("d_info", None, -7), ("nb", 0, -8), ("nb_inner", 17, -9), ("force", 3, -10),
+                           ("d_info", None, -7), ("nb", 0, -8), ("nb_inner", 33, -9), ("force", 3, -10),
                            ("min_width", -1, -11), ("max_widths", 4, -12), ("max_widths", -1, -13),
                            ("n_widths", None, -14), ("d_work", None, -15), ("work_bytes", 16, -16)]:
         kw = dict(base)
@@ -175,7 +180,7 @@ def test_gmres_ir_argument_checks(lib):
                            ("dx", None, -6), ("precision", 3, -7), ("solver", 3, -8), ("tol", -1.0, -9),
                            ("tol", float("nan"), -9), ("max_outer", -1, -10), ("max_krylov", 0, -11),
                            ("max_krylov", mlu.MLU_GMRES_MAX_KRYLOV + 1, -11), ("gmres_tol", -1.0, -12),
-                           ("variant", 3, -13), ("nb", 0, -14), ("nb_inner", 17, -15), ("d_ipiv", None, -16),
+                           ("variant", 3, -13), ("nb", 0, -14), ("nb_inner", 33, -15), ("d_ipiv", None, -16),
                            ("d_info", None, -17), ("h_outer", None, -18), ("h_inner", None, -19),
                            ("h_berr", None, -20), ("d_work", None, -21), ("work_bytes", 16, -22)]:
         kw = dict(base)

@@ -404,7 +404,7 @@ def test_empty_and_degenerate_shapes():
             ipiv = torch.zeros(1, dtype=torch.int32, device=DEV)
             work = mlu.workspace(DEV)
             rc = mlu.mlu_dgetrf(mlu._stream(), m, n, dA.data_ptr() if dA.numel() else 1, max(n, 1),
-                                ipiv.data_ptr(), info.data_ptr(), 0, 4, 0, None, 0, -1, work.data_ptr(),
+                                ipiv.data_ptr(), info.data_ptr(), 0, 4, 0, 0, None, 0, -1, work.data_ptr(),
                                 work.numel())
             assert rc == 0
             assert int(host(info)[0]) == 0
