@@ -40,6 +40,7 @@ extern "C" {
 #endif
 
 #define MLU_ERR_HIP (-1000)
+#define MLU_ERR_NOINIT (-1001)  /* mlu_init has not run on the current device */
 
 /* Device-side status written to *d_info (besides 0 and j > 0, see mlu_dgetrf). */
 #define MLU_INFO_SYNC_TIMEOUT (-999)  /* a cross-workgroup wait exceeded its bound */
@@ -149,6 +150,25 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
 int mlu_dgetrf(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
                int variant, int nb, int nb_inner, int inner, const int32_t *h_schedule, int n_schedule,
                int iters_limit, void *d_work, size_t work_bytes);
+
+/*
+ * mlu_dgetrf for callers that cannot allocate: code under stream capture,
+ * serving loops and harnesses that forbid device allocation.  Same arguments
+ * and results as mlu_dgetrf without the workspace (arguments 1..14 numbered
+ * as there): the factorization's scratch (the panel kernel's exchange slots,
+ * the tile queues, about 60 KB) lives in a fixed-size device array of the
+ * library, one per device, held until the process ends; no call allocates or
+ * frees device memory.  Its size does not depend on m or n, so the only size
+ * limit is mlu_dgetrf's (m <= 33280, argument 2).  mlu_init (or a workspace
+ * query) must have run on the current device first: it resolves the array's
+ * device address and creates the library stream; otherwise the call returns
+ * MLU_ERR_NOINIT and enqueues nothing.  Every call on a device shares that
+ * device's array (cleared by a kernel at the start of each call): calls that
+ * overlap in time on one device race, whatever their streams.
+ */
+int mlu_dgetrf_noalloc(void *stream, int m, int n, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
+                       int variant, int nb, int nb_inner, int inner, const int32_t *h_schedule, int n_schedule,
+                       int iters_limit);
 
 /*
  * LU with partial pivoting by the look-ahead variant with early termination of

@@ -28,6 +28,10 @@
 #include <mutex>
 #include <vector>
 
+// The no-allocation entry point's scratch array (see init_static_scratch).
+constexpr size_t kScratchBytes = (sizeof(mlu::Workspace) + 4095) / 4096 * 4096;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace mlu {
 namespace {
 
@@ -383,7 +387,47 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
   return hipSuccess;
 }
 
+// Scratch of mlu_dgetrf_noalloc: one factorization workspace per device in a
+// file-scope device array (each device holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: on the host it
+// is a stand-in, not a device address.  init_static_scratch resolves the
+// array's address on the current device once, and every use goes through it.
+std::mutex g_scratch_mu;
+void* g_scratch[64];
+
+// The current device's scratch address, or null before mlu_init ran on it.
+void* static_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[dev];
+}
+
+// Whether mlu_init has created the library stream of the current device.
+bool aux_ready() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  return g_aux[dev].ready;
+}
+
 }  // namespace
+
+// Resolve the scratch array's address on the current device (once per device).
+hipError_t init_static_scratch() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] != nullptr) return hipSuccess;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch));
+  if (e != hipSuccess) return e;
+  if (ptr == nullptr) return hipErrorInvalidSymbol;
+  g_scratch[dev] = ptr;
+  return hipSuccess;
+}
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes) {
   const size_t nw = bytes / 4;
@@ -402,7 +446,8 @@ int mlu_version(void) { return 200; }
 
 int mlu_init(void) {
   AuxStreams* aux = nullptr;
-  return get_aux(&aux) == hipSuccess ? 0 : MLU_ERR_HIP;
+  if (get_aux(&aux) != hipSuccess) return MLU_ERR_HIP;
+  return init_static_scratch() == hipSuccess ? 0 : MLU_ERR_HIP;
 }
 
 int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t* bytes) {
@@ -500,6 +545,35 @@ int mlu_dgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv,
   const int rc = getrf_entry(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, MLU_PREC_FP64,
                              h_schedule, n_schedule, iters_limit, d_work, work_bytes, 0);
   return rc;
+}
+
+int mlu_dgetrf_noalloc(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info,
+                       int variant, int nb, int nb_inner, int inner, const int32_t* h_schedule, int n_schedule,
+                       int iters_limit) {
+  const int mn = m < n ? m : n;
+  if (m < 0 || m > kPanelMaxRows) return -2;
+  if (n < 0) return -3;
+  if (mn > 0 && !dA) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (mn > 0 && !d_ipiv) return -6;
+  if (!d_info) return -7;
+  if (variant < MLU_RL || variant > MLU_LA) return -8;
+  if (nb < 1) return -9;
+  if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
+  if (inner != MLU_RL && inner != MLU_LL) return -11;
+  if (h_schedule) {
+    if (n_schedule < 1) return -13;
+    for (int i = 0; i < n_schedule; ++i)
+      if (h_schedule[i] < 1) return -12;
+  }
+  if (iters_limit < -1) return -14;
+  // the device's scratch array (and, for the look-ahead variant, the library
+  // stream) must have been set up by mlu_init: nothing is created here
+  void* ws = static_scratch();
+  if (ws == nullptr || !aux_ready()) return MLU_ERR_NOINIT;
+  static_assert(sizeof(Workspace) <= kScratchBytes, "the scratch array holds one workspace");
+  return getrf_run(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, MLU_PREC_FP64, h_schedule,
+                   n_schedule, iters_limit, ws);
 }
 
 int mlu_dsgetrf(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,

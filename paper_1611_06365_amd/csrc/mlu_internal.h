@@ -171,5 +171,6 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
 int getrf_run(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info, int variant,
               int nb, int nb_inner, int inner, int precision, const int32_t* h_schedule, int n_schedule,
               int iters_limit, void* d_work);
+hipError_t init_static_scratch();
 
 }  // namespace mlu

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmlu.so")
 MLU_RL, MLU_LL, MLU_LA = 0, 1, 2
 VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA}
 MLU_ERR_HIP = -1000
+MLU_ERR_NOINIT = -1001
 MLU_INFO_SYNC_TIMEOUT = -999
 MLU_INFO_BAD_PIVOT = -998
 MLU_MAX_NB_INNER = 32
@@ -32,6 +33,7 @@ _SIGNATURES = {
     "mlu_init": ([], _i),
     "mlu_dgetrf_workspace": ([_i, _i, _i, _i, _i, ctypes.POINTER(_sz)], _i),
     "mlu_dgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
+    "mlu_dgetrf_noalloc": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _i], _i),
     "mlu_dsgetrf": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _i, _vp, _sz], _i),
     "mlu_select": ([_vp, _i, _i, _i, _i, _vp, _vp, _vp], _i),
     "mlu_dgetrf_et": ([_vp, _i, _i, _vp, _i, _vp, _vp, _i, _i, _i, _i, _vp, _i, _vp, _vp, _sz], _i),
@@ -100,6 +102,12 @@ def mlu_dgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inn
                iters_limit, d_work, work_bytes) -> int:
     return _call("mlu_dgetrf", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, h_schedule,
                  n_schedule, iters_limit, d_work, work_bytes)
+
+
+def mlu_dgetrf_noalloc(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, h_schedule, n_schedule,
+                       iters_limit) -> int:
+    return _call("mlu_dgetrf_noalloc", stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner,
+                 h_schedule, n_schedule, iters_limit)
 
 
 def mlu_dsgetrf(stream, m, n, dA, lda, d_ipiv, d_info, variant, nb, nb_inner, inner, precision, h_schedule,

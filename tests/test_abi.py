@@ -186,3 +186,31 @@ def test_gmres_ir_argument_checks(lib):
         kw = dict(base)
         kw[key] = bad
         assert mlu.mlu_dsgesv_gmres_ir(*kw.values()) == code, key
+
+
+def test_noalloc_argument_checks(lib):
+    base = dict(stream=None, m=8, n=8, dA=1024, lda=8, d_ipiv=2048, d_info=4096, variant=2, nb=4, nb_inner=0,
+                inner=0, h_schedule=None, n_schedule=0, iters_limit=-1)
+    for key, bad, code in [("m", -1, -2), ("m", 40000, -2), ("n", -1, -3), ("dA", None, -4), ("lda", 7, -5),
+                           ("d_ipiv", None, -6), ("d_info", None, -7), ("variant", 3, -8), ("nb", 0, -9),
+                           ("nb_inner", 33, -10), ("inner", 2, -11), ("iters_limit", -2, -14)]:
+        kw = dict(base)
+        kw[key] = bad
+        assert mlu.mlu_dgetrf_noalloc(*kw.values()) == code, key
+    arr = (ctypes.c_int32 * 2)(4, 0)
+    kw = dict(base, h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=2)
+    assert mlu.mlu_dgetrf_noalloc(*kw.values()) == -12
+    kw = dict(base, h_schedule=ctypes.cast(arr, ctypes.c_void_p), n_schedule=0)
+    assert mlu.mlu_dgetrf_noalloc(*kw.values()) == -13
+    if os.environ.get("HIP_VISIBLE_DEVICES", None) == "" or not _has_gpu():
+        # no device here: nothing was set up, and nothing is enqueued
+        assert mlu.mlu_dgetrf_noalloc(*base.values()) == mlu.MLU_ERR_NOINIT
+
+
+def _has_gpu():
+    try:
+        import torch
+
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
