@@ -31,12 +31,13 @@ METRIC = "GFLOP/s & %MFMA roofline at n=16384 (FP64 vs mixed+refine @1e-13); bat
 FP64_PEAK_TFLOPS = 78.6
 # the traced launches: the outer trailing updates carrying nearly all flops
 KERNEL_LABEL = {
-    "la": "k_gemm_queue (RU2 as a persistent tile queue on the CUs the panel stream leaves, joined by the panel's "
-          "workgroups after PF3; the last iteration's k_gemm_trailing), v_mfma_f64_16x16x4f64",
+    "la": "k_gemm_queue_whole (RU2 as a persistent tile queue on the CUs the panel stream leaves, pipelined across "
+          "tiles, joined by the panel's workgroups after PF3; the last iteration's k_gemm_trailing), "
+          "v_mfma_f64_16x16x4f64",
     "rl": "k_gemm_trailing (RL3), v_mfma_f64_16x16x4f64",
     "ll": "k_gemm_trailing (LL2), v_mfma_f64_16x16x4f64",
 }
-TRAFFIC_KERNEL = {"la": "k_gemm_queue", "rl": "k_gemm_trailing", "ll": "k_gemm_trailing"}
+TRAFFIC_KERNEL = {"la": "k_gemm_queue_whole", "rl": "k_gemm_trailing", "ll": "k_gemm_trailing"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_queue_la_n16384_traffic.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1611_06365_amd", "csrc", "gemm.hip")
 

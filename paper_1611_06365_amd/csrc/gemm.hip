@@ -645,6 +645,178 @@ __global__ __launch_bounds__(256, 2) void k_gemm_small(int m, int n, int k, cons
   gemm_tile_small<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
+// The FP64 persistent tile loop, pipelined across tiles, for launches whose
+// tiles and K stages are all whole (m and n multiples of 128, k of 16: the
+// look-ahead trailing updates at orders that are multiples of the block size,
+// with 16-byte aligned operands): the ticket of the
+// next tile is taken while the current tile's first K stage runs (issued
+// before its products, resolved after them), the next tile's first K stage is
+// loaded while the current tile's last stage runs, and the epilogue stores each
+// accumulator of the current tile and loads the same element of the next
+// tile's C in its place, so the stores drain while the next loads are in
+// flight.  Each tile's arithmetic is that of gemm_tile (the same K stages, the
+// same MFMA order), so results do not depend on which workgroup took a tile.
+// `x` is the queue the workgroup draws from; only thread 0 uses it.
+__device__ __forceinline__ void queue_loop_f64_whole(int k, const double* __restrict__ A, int lda,
+                                                     const double* __restrict__ B, int ldb, double* __restrict__ C,
+                                                     int ldc, int tiles_m, int tiles_n, unsigned* __restrict__ q,
+                                                     int x) {
+  __shared__ double As[2][BM * LDS_A];
+  __shared__ double Bs[2][BK * LDS_B];
+  __shared__ int s_next;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ar = tid >> 1, ac = (tid & 1) * 8;
+  const int br = tid >> 4, bc = (tid & 15) * 8;
+  const long long T = (long long)tiles_m * tiles_n;
+  // thread 0, holding a ticket of queue x: its tile, or the next queue's
+  // ticket while this one is exhausted; -1 once every queue is
+  auto walk = [&](unsigned ticket) -> int {
+    for (int tries = 0;; ++tries) {
+      const long long lo = T * x / kXcd, hi = T * (x + 1) / kXcd;
+      if (lo + (long long)ticket < hi) return (int)(lo + ticket);
+      if (tries + 1 >= kXcd) return -1;
+      x = (x + 1) & (kXcd - 1);
+      ticket = atomicAdd(&q[x * kQueueStride], 1u);
+    }
+  };
+  double ra[8], rb[8];
+  // stage k0 of the tile at (r0, c0) into registers, B negated (k is a
+  // multiple of 16: every stage is whole)
+  auto gload = [&](int r0, int c0, int k0) {
+    const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(r0 + ar) * lda + k0 + ac);
+    const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + c0 + bc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const double2 xa = pa[e];
+      ra[2 * e] = xa.x;
+      ra[2 * e + 1] = xa.y;
+      const double2 yb = pb[e];
+      rb[2 * e] = -yb.x;
+      rb[2 * e + 1] = -yb.y;
+    }
+  };
+  auto sstore = [&](int buf) {
+    double* pa = &As[buf][ar * LDS_A + ac];
+    double* pb = &Bs[buf][br * LDS_B + bc];
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      *reinterpret_cast<double2*>(pa + e) = make_double2(ra[e], ra[e + 1]);
+      *reinterpret_cast<double2*>(pb + e) = make_double2(rb[e], rb[e + 1]);
+    }
+  };
+  // lane (li, lq) of a 16 x 16 f64 accumulator block holds rows lq + 4 r of column li
+  auto cptr = [&](int r0, int c0) { return C + (size_t)(r0 + wm * 64 + lq) * ldc + c0 + wn * 64 + li; };
+
+  if (tid == 0) s_next = walk(atomicAdd(&q[x * kQueueStride], 1u));
+  __syncthreads();
+  const int t = __builtin_amdgcn_readfirstlane(s_next);
+  if (t < 0) return;
+  int tm, tn;
+  group_coords(t, tiles_m, tiles_n, tm, tn);
+  int row0 = tm * BM, col0 = tn * BN;
+  v4d acc[4][4];
+  {
+    const double* cb = cptr(row0, col0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = cb[(size_t)(i * 16 + 4 * r) * ldc + j * 16];
+  }
+  gload(row0, col0, 0);
+  sstore(0);
+  __syncthreads();   // also: every thread has read s_next before it is written again
+  int buf = 0;
+  const int nk = (k + BK - 1) / BK;
+  while (true) {
+    unsigned tk = 0;
+    if (tid == 0) tk = atomicAdd(&q[x * kQueueStride], 1u);   // resolved after stage 0's products
+    int next = -1, nrow0 = 0, ncol0 = 0;
+    for (int kt = 0; kt < nk; ++kt) {
+      const bool last = kt + 1 == nk;
+      if (!last) gload(row0, col0, (kt + 1) * BK);
+      else if (next >= 0) gload(nrow0, ncol0, 0);
+      double a[2][4], b[2][4];
+      auto frag = [&](int st, int qq) {
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) {
+          a[qq][blk] = As[buf][(wm * 64 + blk * 16 + li) * LDS_A + 4 * lq + st];
+          b[qq][blk] = Bs[buf][(4 * lq + st) * LDS_B + wn * 64 + blk * 16 + li];
+        }
+      };
+      frag(0, 0);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (st + 1 < 4) frag(st + 1, (st + 1) & 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st & 1][i], b[st & 1][j], acc[i][j], 0, 0, 0);
+      }
+      if (kt == 0 && tid == 0) s_next = walk(tk);
+      if (!last || next >= 0) sstore(buf ^ 1);
+      __syncthreads();
+      if (kt == 0) {   // the next tile is known once stage 0's barrier has passed
+        next = __builtin_amdgcn_readfirstlane(s_next);
+        if (next >= 0) {
+          int ntm, ntn;
+          group_coords(next, tiles_m, tiles_n, ntm, ntn);
+          nrow0 = ntm * BM;
+          ncol0 = ntn * BN;
+        }
+      }
+      buf ^= 1;
+    }
+    // epilogue: store this tile, loading the next tile's C into the same registers
+    double* cb = cptr(row0, col0);
+    if (next >= 0) {
+      const double* nb = cptr(nrow0, ncol0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            cb[(size_t)(i * 16 + 4 * r) * ldc + j * 16] = acc[i][j][r];
+            acc[i][j][r] = nb[(size_t)(i * 16 + 4 * r) * ldc + j * 16];
+          }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cb[(size_t)(i * 16 + 4 * r) * ldc + j * 16] = acc[i][j][r];
+      break;
+    }
+    if (nk == 1) {   // with one stage the next tile was known too late to load it during this one
+      gload(nrow0, ncol0, 0);
+      sstore(buf);
+      __syncthreads();
+    }
+    row0 = nrow0;
+    col0 = ncol0;
+  }
+}
+
+// The persistent FP64 update when every tile and stage is whole and the
+// operands allow 16-byte loads (the host checks): the pipelined tile loop above, under
+// its own kernel name so that a kernel trace tells the two forms apart.
+__global__ __launch_bounds__(256, 2) void k_gemm_queue_whole(int k, const double* __restrict__ A, int lda,
+                                                             const double* __restrict__ B, int ldb,
+                                                             double* __restrict__ C, int ldc, int tiles_m,
+                                                             int tiles_n, unsigned* __restrict__ q,
+                                                             unsigned* __restrict__ clear, int reserve) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && clear != nullptr && tid < kXcd) clear[tid * kQueueStride] = 0u;
+  if (reserve > 0 && (int)(hw_cu_id() & 7u) < reserve) return;   // uniform over the workgroup
+  queue_loop_f64_whole(k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, q, (int)hw_xcc_id());
+}
+
 // Persistent form for the look-ahead variant's RU2: queue x holds the logical
 // tiles [x T / 8, (x + 1) T / 8); a workgroup takes tickets from the queue of
 // the XCD it runs on, then from the other queues in turn, and leaves when all
@@ -825,6 +997,9 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
     else
       hipLaunchKernelGGL((k_gemm_queue<false, kPrecBF16>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
                          ldc, tiles_m, tiles_n, q, clear, reserve);
+  } else if (vec && m % BM == 0 && n % BN == 0 && k % BK == 0) {
+    hipLaunchKernelGGL(k_gemm_queue_whole, dim3(grid), dim3(256), 0, s, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n,
+                       q, clear, reserve);
   } else {
     if (vec)
       hipLaunchKernelGGL((k_gemm_queue<true, kPrecF64>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,

@@ -225,8 +225,11 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       // T_RU: RU1, then RU2 as a persistent tile queue that leaves CUs to T_PF.
       // RU2 starts once PF2 is done: PF2's tiles would otherwise take CUs that
       // the persistent RU2 workgroups cannot get back until they finish,
-      // which costs RU2 more than the wait (measured at n = 16384)
+      // which costs RU2 more than the wait (measured at n = 16384; starting
+      // RU2 first only in the iterations where it is the longer chain was
+      // measured too and is slower)
       const int c0 = jn + bp;
+      const int mr = c.m - jn, nr = c.n - c0;
       unsigned* q = c.queue->ctr[k % kQueueSlots];
       unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
       if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
@@ -235,7 +238,6 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
       MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));         // PF1, PF2
       MLU_TRY(hipEventRecord(aux->pf2, s1));
-      const int mr = c.m - jn, nr = c.n - c0;
       MLU_TRY(hipStreamWaitEvent(s0, aux->pf2, 0));
       int tid = -1;
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
