@@ -386,10 +386,13 @@ int mlu_dlaswp(void *stream, int m, int ncols, double *dA, int lda, int k1, int 
                int32_t *d_info);
 
 /*
- * Unblocked factorization of one m x bw block (1 <= bw <= 16, bw <= m): the
- * diagonal-block kernel (LU_unb of Fig. "LU", left) alone.  Interchanges are
- * applied inside the block only; d_ipiv[c] (c < bw) receives the 1-based row.
- * *d_info as in mlu_dgetrf.  Needs bw <= m and the mlu_dgetrf workspace.
+ * Unblocked factorization of one m x bw block (bw <= m; 1 <= bw <= 16 at any
+ * m <= 33280, 17 <= bw <= 32 for m <= 8192, else -3 or -2): the
+ * diagonal-block kernel (LU_unb of Fig. "LU", left) alone, holding the block
+ * in registers (two rows per thread for up to 16 columns, one row per thread
+ * for up to 32).  Interchanges are applied inside the block only; d_ipiv[c]
+ * (c < bw) receives the 1-based row.  *d_info as in mlu_dgetrf.  Needs the
+ * mlu_dgetrf workspace.
  */
 int mlu_dgetf2_block(void *stream, int m, int bw, double *dA, int lda, int32_t *d_ipiv, int32_t *d_info,
                      void *d_work, size_t work_bytes);

@@ -139,14 +139,15 @@ struct Ctx {
 // left), inside a panel with cl columns to the block's left and cr to its
 // right: the block's interchanges are applied to all of them, and the block's
 // rows of the first ns right columns are solved with its unit lower triangle
-// (the inner RL2).  A block wider than the register-resident kernel's 16
-// columns is eliminated in two register passes, right-looking over its
-// columns: the first 16 columns (their rows of the other half solved), a
+// (the inner RL2).  The register-resident kernel holds up to 16 columns at any
+// height and up to 32 in panels of at most kPanelWideRows rows; a wider block
+// in a taller panel is eliminated in two register passes, right-looking over
+// its columns: the first 16 columns (their rows of the other half solved), a
 // rank-16 update of the other half, then that half; the second pass solves
 // the right columns with the whole 32 x 32 triangle.
 hipError_t factor_block(hipStream_t s, const Ctx& c, int jj, int bw, int cl, int cr, int ns,
                         const int32_t* skip = nullptr) {
-  if (bw <= kPanelRegCols)
+  if (bw <= kPanelRegCols || c.m - jj <= kPanelWideRows)
     return panel_factor(s, c.at(jj, jj), c.lda, c.m - jj, bw, jj, c.ipiv, c.info, c.work, ++*c.epoch, cl, cr, skip,
                         ns);
   const int h1 = kPanelRegCols, h2 = bw - kPanelRegCols;
@@ -686,7 +687,8 @@ int mlu_dlaswp(void* stream, int m, int ncols, double* dA, int lda, int k1, int 
 int mlu_dgetf2_block(void* stream, int m, int bw, double* dA, int lda, int32_t* d_ipiv, int32_t* d_info,
                      void* d_work, size_t work_bytes) {
   if (m < 0 || m > kPanelMaxRows) return -2;
-  if (bw < 0 || bw > kPanelRegCols || bw > m) return -3;
+  if (bw < 0 || bw > kPanelWideCols || bw > m) return -3;
+  if (bw > kPanelRegCols && m > kPanelWideRows) return -2;
   if (bw > 0 && !dA) return -4;
   if (lda < (bw > 1 ? bw : 1)) return -5;
   if (bw > 0 && !d_ipiv) return -6;

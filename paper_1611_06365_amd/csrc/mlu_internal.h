@@ -27,9 +27,15 @@ __device__ __forceinline__ void lds_sync() {
 // workgroups of one panel launch and the tallest panel they hold (the leader
 // holds 512 rows, every other workgroup 1024).
 constexpr int kPanelMaxCols = 32;   // exchange-area width
-constexpr int kPanelRegCols = 16;   // widest block the kernel holds in registers
+constexpr int kPanelRegCols = 16;   // block width of the kernel at any height
 constexpr int kPanelMaxWG = 33;
 constexpr int kPanelMaxRows = 512 + (kPanelMaxWG - 1) * 1024;
+// The kernel also holds blocks of up to kPanelWideCols columns in registers,
+// one row per thread, in panels of at most kPanelWideRows rows (16 workgroups
+// of 512 rows).
+constexpr int kPanelWideCols = 32;
+constexpr int kPanelWideWG = 16;
+constexpr int kPanelWideRows = kPanelWideWG * 512;
 
 // One published value: {value, aux, tag}, written and read as one 16-byte
 // device-coherent access so that the tag and the value arrive together.

@@ -230,8 +230,10 @@ constexpr unsigned off_spec(int c, int t) {
 }
 constexpr unsigned off_verify(int w) { return (unsigned)offsetof(PanelWork, verify) + (unsigned)(w * 16); }
 
-// worker that holds a given row (rows as laid out above)
-__device__ __forceinline__ int worker_of(int r) { return r < NT ? 0 : 1 + (r - NT) / (2 * NT); }
+// worker that holds a given row (rows as laid out above; KR rows per thread
+// outside the leader)
+template <int KR>
+__device__ __forceinline__ int worker_of(int r) { return r < NT ? 0 : 1 + (r - NT) / (KR * NT); }
 
 struct PanelShared {
   double val[2][NWAVE];
@@ -263,7 +265,7 @@ __device__ __forceinline__ void poll_chunks(const char* base, const unsigned (&o
   }
 }
 
-template <int BW, int MAXW>
+template <int BW, int MAXW, int KR>
 struct Panel {
   static constexpr int kPoll = (MAXW * BW + kWave - 1) / kWave;   // candidate chunks per lane
 
@@ -278,12 +280,12 @@ struct Panel {
   double (*s_drow)[BW];
   double (*s_prow)[BW];
   PanelShared* sh;
-  double v[2][BW];
-  int rows[2];
+  double v[KR][BW];
+  int rows[KR];
 
   __device__ __forceinline__ void load() {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       const bool ok = rows[k] < m;
       const double* src = A + (size_t)(ok ? rows[k] : 0) * lda;
 #pragma unroll
@@ -292,7 +294,7 @@ struct Panel {
   }
   __device__ __forceinline__ void store() {
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < KR; ++k)
       if (rows[k] < m) {
         double* dst = A + (size_t)rows[k] * lda;
 #pragma unroll
@@ -302,7 +304,7 @@ struct Panel {
   }
   __device__ __forceinline__ void rotate() {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       double t[U];
 #pragma unroll
       for (int j = 0; j < U; ++j) t[j] = v[k][j];
@@ -324,7 +326,7 @@ struct Panel {
     bv = -1.0;
     br = kRowNone;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       const int r = rows[k];
       if (r < m && r >= c) {
         const double a = fabs(v[k][u]);
@@ -336,7 +338,7 @@ struct Panel {
     }
     wave_argmax(bv, br);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       if (rows[k] == br) lds_put_row<BW>(s_cand[par][wave], v[k]);
       if (rows[k] == c) lds_put_row<BW>(s_drow[par], v[k]);
     }
@@ -370,12 +372,12 @@ struct Panel {
   __device__ __forceinline__ void apply(int c, int lim, int p, const double* prow, const double* drow) {
     const double piv = prow[u];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       if (rows[k] == c) lds_get_row<BW>(v[k], prow);
       else if (rows[k] == p) lds_get_row<BW>(v[k], drow);
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < KR; ++k) {
       const int r = rows[k];
       if (r > c && r < m) {
         double l = v[k][u];
@@ -430,7 +432,7 @@ struct Panel {
               double gv = lane < nwg ? chunk_val(got[0]) : -1.0;
               int gr = lane < nwg ? got[0][2] : kRowNone;
               wave_argmax(gv, gr);
-              const int gw = gr == kRowNone ? 0 : worker_of(gr);
+              const int gw = gr == kRowNone ? 0 : worker_of<KR>(gr);
               if (lane == 0) sh->p[par] = gr;
 #pragma unroll
               for (int i = 0; i < kPoll; ++i) {
@@ -549,7 +551,7 @@ struct Panel {
           const double piv = pr[u];
           const double apiv = fabs(piv);
 #pragma unroll
-          for (int k = 0; k < 2; ++k) {
+          for (int k = 0; k < KR; ++k) {
             const int r = rows[k];
             if (r < m) {
               if (fabs(v[k][u]) > apiv && fail > c) fail = c;
@@ -606,14 +608,15 @@ struct Panel {
 // columns to the block's left.  No other worker touches these columns during
 // the launch.
 constexpr int kMvCols = 64;
-constexpr int kTriMax = 2 * kPanelRegCols;   // rows of the largest triangle solved
+constexpr int kTriMax = kPanelWideCols;   // rows of the largest triangle solved
+static_assert(2 * kPanelRegCols <= kTriMax, "a two-pass block's triangle fits");
 
 struct EpilogueShared {
-  double mv[2 * kPanelRegCols][kMvCols];
+  double mv[2 * kPanelWideCols][kMvCols];
   double T[kTriMax][kTriMax + 1];
-  int slot[kPanelRegCols];
-  int row[2 * kPanelRegCols];
-  int label[2 * kPanelRegCols];
+  int slot[kPanelWideCols];
+  int row[2 * kPanelWideCols];
+  int label[2 * kPanelWideCols];
   int any;
 };
 
@@ -675,7 +678,7 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, in
       // slot's entry is never written back), all loads before the first store
       const int gc = min(g, ncols - 1);
       const int colc = gc < cl ? gc - cl : bw + (gc - cl);
-      constexpr int kPer = 2 * kPanelRegCols / (NT / kMvCols);
+      constexpr int kPer = 2 * BW / (NT / kMvCols);
       double mvv[kPer];
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
@@ -715,9 +718,12 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, in
     for (int r = 0; r < TM; ++r) x[r] = (r < nt) ? colp[(size_t)r * lda] : 0.0;
     // column by column: x[r] -= T[r][q] x[q] for r > q, so every x[r]
     // receives its terms in the order q = 0, 1, ... of row-wise substitution;
-    // T is read through an LDS pointer (ds_read, not flat loads)
+    // T is read through an LDS pointer (ds_read, not flat loads), column q at
+    // its step (the scheduling barrier keeps the compiler from reading the
+    // whole triangle into registers up front)
 #pragma unroll
     for (int q = 0; q < TM - 1; ++q) {
+      __builtin_amdgcn_sched_barrier(0);
       if (q < nt - 1) {
         const double xq = x[q];
 #pragma unroll
@@ -731,7 +737,7 @@ __device__ __noinline__ void panel_epilogue(double* __restrict__ Ag, int lda, in
   }
 }
 
-template <int BW, int MAXW>
+template <int BW, int MAXW, int KR>
 __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, int m, int bw, int row0,
                                               int32_t* __restrict__ ipiv, int32_t* __restrict__ info,
                                               PanelWork* __restrict__ work, int nwg, unsigned epoch, int cl,
@@ -745,7 +751,7 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   __shared__ __attribute__((aligned(16))) double s_prow[2][BW];
   __shared__ PanelShared sh;
 
-  Panel<BW, MAXW> P;
+  Panel<BW, MAXW, KR> P;
   P.A = A;
   P.lda = lda;
   P.m = m;
@@ -765,10 +771,11 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
   P.sh = &sh;
   if (P.wg == 0) {
     P.rows[0] = P.tid;
-    P.rows[1] = kRowNone;
+#pragma unroll
+    for (int k = 1; k < KR; ++k) P.rows[k] = kRowNone;
   } else {
-    P.rows[0] = NT + (P.wg - 1) * 2 * NT + P.tid;
-    P.rows[1] = P.rows[0] + NT;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) P.rows[k] = NT + (P.wg - 1) * KR * NT + k * NT + P.tid;
   }
   if (P.tid == 0) sh.zero_col = -1;
   P.load();
@@ -798,8 +805,12 @@ __global__ __launch_bounds__(NT) void k_panel(double* __restrict__ A, int lda, i
 #pragma unroll
         for (int c = 0; c < BW; ++c) es.T[lb + P.tid][lb + c] = (c < P.tid) ? P.v[0][c] : 0.0;
       }
-      if (lb == 0) panel_epilogue<BW, 0>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
-      else panel_epilogue<BW, kPanelRegCols>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
+      if constexpr (BW > kPanelRegCols) {
+        panel_epilogue<BW, 0>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
+      } else {
+        if (lb == 0) panel_epilogue<BW, 0>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
+        else panel_epilogue<BW, kPanelRegCols>(A, lda, bw, cl, cr, ns, sh.piv, P.tid, &es);
+      }
     }
   }
 }
@@ -808,14 +819,21 @@ template <int BW>
 hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int row0, int32_t* ipiv,
                         int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, int ns, int lb,
                         const int32_t* skip) {
-  const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
-  if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
-  if (nwg <= 16)
-    hipLaunchKernelGGL((k_panel<BW, 16>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work, nwg,
-                       epoch, cl, cr, ns, lb, skip);
-  else
-    hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
+  if constexpr (BW > kPanelRegCols) {   // wide blocks: one row per thread, at most kPanelWideWG workers
+    const int nwg = m <= NT ? 1 : 1 + (m - NT + NT - 1) / NT;
+    if (nwg > kPanelWideWG) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_panel<BW, kPanelWideWG, 1>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
                        work, nwg, epoch, cl, cr, ns, lb, skip);
+  } else {
+    const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
+    if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
+    if (nwg <= 16)
+      hipLaunchKernelGGL((k_panel<BW, 16, 2>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work,
+                         nwg, epoch, cl, cr, ns, lb, skip);
+    else
+      hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG, 2>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv,
+                         info, work, nwg, epoch, cl, cr, ns, lb, skip);
+  }
   return hipGetLastError();
 }
 
@@ -825,12 +843,15 @@ hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int ro
                         int32_t* info, PanelWork* work, unsigned epoch, int cl, int cr, const int32_t* skip,
                         int ns, int lb) {
   if (m <= 0 || bw <= 0) return hipSuccess;
-  if (bw > kPanelRegCols || bw > m || m > kPanelMaxRows || cl < 0 || cr < 0) return hipErrorInvalidValue;
+  if (bw > kPanelWideCols || bw > m || m > kPanelMaxRows || cl < 0 || cr < 0) return hipErrorInvalidValue;
+  if (bw > kPanelRegCols && m > kPanelWideRows) return hipErrorInvalidValue;
   if (ns < 0) ns = cr;
-  if (ns > cr || (lb != 0 && lb != kPanelRegCols) || lb > cl) return hipErrorInvalidValue;
+  if (ns > cr || (lb != 0 && lb != kPanelRegCols) || lb > cl || (lb != 0 && bw > kPanelRegCols))
+    return hipErrorInvalidValue;
   ipiv += row0;
   if (bw <= 8) return launch_panel<8>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
-  return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
+  if (bw <= 16) return launch_panel<16>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
+  return launch_panel<32>(s, A, lda, m, bw, row0, ipiv, info, work, epoch, cl, cr, ns, lb, skip);
 }
 
 size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }

@@ -83,7 +83,8 @@ def test_other_argument_checks(lib):
     assert mlu.mlu_dgetrs(None, 4, 2, 1024, 3, 2048, 4096, 2) == -5
     assert mlu.mlu_dgemm_update(None, 4, 4, 4, 1024, 3, 2048, 4, 4096, 4) == -6
     assert mlu.mlu_dlaswp(None, 4, 4, 1024, 4, 2, 1, 2048, None) == -7
-    assert mlu.mlu_dgetf2_block(None, 32, 17, 1024, 17, 2048, 4096, 8192, 1 << 20) == -3
+    assert mlu.mlu_dgetf2_block(None, 40, 33, 1024, 33, 2048, 4096, 8192, 1 << 20) == -3
+    assert mlu.mlu_dgetf2_block(None, 8193, 17, 1024, 17, 2048, 4096, 8192, 1 << 20) == -2
     assert mlu.mlu_dgetf2_block(None, 4, 8, 1024, 8, 2048, 4096, 8192, 1 << 20) == -3
 
 

@@ -261,3 +261,85 @@ def test_lu_ir_stops_when_corrections_diverge():
         assert np.isfinite(be) and be < 1e-1 and np.all(np.isfinite(x))
     else:
         assert be <= 1e-13
+
+
+# ------------------------------------------------------------ the 32-column diagonal-block kernel
+def getf2(A):
+    dA = dev(A)
+    ipiv, info = mlu.getf2_block(dA)
+    bw = A.shape[1]
+    return host(dA), (host(ipiv)[:bw] - 1).tolist(), int(host(info)[0])
+
+
+@pytest.mark.parametrize("m", [17, 32, 63, 64, 65, 300, 512, 513, 1024, 1025, 3000, 8192])
+@pytest.mark.parametrize("bw", [17, 24, 32])
+def test_wide_block_uniform(m, bw):
+    if bw > m:
+        pytest.skip("bw > m")
+    A = G.uniform01(m, bw, seed=m + 3 * bw)
+    F, piv, info = getf2(A)
+    R = A.copy()
+    opiv = O.lu_unb(R)
+    assert info == 0
+    assert piv == opiv
+    assert np.abs(F - R).max() <= 1e-13 * max(1.0, np.abs(R).max())
+
+
+@pytest.mark.parametrize("m,bw", [(40, 32), (2000, 32), (5000, 24), (8192, 32)])
+def test_wide_block_known_answer_exact(m, bw):
+    A, perm, L, U = G.known_answer(m, bw, seed=m + bw)
+    F, piv, info = getf2(A)
+    R = A.copy()
+    opiv = O.lu_unb(R)
+    assert info == 0 and piv == opiv
+    assert np.array_equal(F, R)
+
+
+@pytest.mark.parametrize("m,bw,fail_at", [(3000, 32, None), (3000, 32, 0), (3000, 32, 13), (3000, 32, 31),
+                                          (8192, 32, 20), (300, 24, 9), (1000, 32, None)])
+def test_wide_block_speculation_paths(m, bw, fail_at):
+    # as for the 16-column kernel: pivots guessed from the leader's rows; rows
+    # placed below them make the guess fail at column fail_at, and the block
+    # is redone exactly; every path gives the partial-pivoting factors, bit
+    # for bit on this exact input
+    perm = G.leader_perm(m, bw, 64, fail_at, seed=m + bw)
+    A, perm, L, U = G.known_answer(m, bw, seed=m, perm=perm)
+    F, piv, info = getf2(A)
+    R = A.copy()
+    opiv = O.lu_unb(R)
+    assert info == 0 and piv == opiv
+    assert np.array_equal(F, R)
+    assert np.array_equal(O.permutation_of(piv, m)[:bw], perm[:bw])
+
+
+def test_wide_block_ties_and_zero_pivot():
+    W = G.wilkinson_growth(32)
+    F, piv, info = getf2(W)
+    assert piv == list(range(32))
+    R = W.copy()
+    O.lu_unb(R)
+    assert np.array_equal(F, R)
+    Z = G.uniform01(700, 32, seed=3)
+    Z[:, 5] = 0.0
+    Z[:, 0] = 0.0
+    F, piv, info = getf2(Z)
+    R = Z.copy()
+    inf_ = [0]
+    opiv = O.lu_unb(R, info=inf_)
+    assert info == 1 == inf_[0]
+    assert piv == opiv
+    assert np.abs(F - R).max() <= 1e-13
+
+
+@pytest.mark.parametrize("variant", ["rl", "la", "ll"])
+@pytest.mark.parametrize("inner", ["rl", "ll"])
+def test_wide_blocks_inside_the_factorization(variant, inner):
+    # b_i = 32 on a matrix short enough for the 32-column kernel (every panel
+    # at most 8192 rows), pivoting at nearly every column
+    n = 2100
+    A = G.uniform01(n, seed=41)
+    F, piv, info = gpu_getrf(A, variant, 128, 32, inner)
+    R = A.copy()
+    opiv, oinfo = O.getrf(R, variant, nb=128, inner=(inner, 32))
+    assert info == oinfo == 0 and piv == opiv
+    assert np.abs(F - R).max() <= 1e-11 * np.abs(R).max()
