@@ -38,7 +38,8 @@ KERNEL_LABEL = {
     "ll": "k_gemm_trailing (LL2), v_mfma_f64_16x16x4f64",
 }
 TRAFFIC_KERNEL = {"la": "k_gemm_queue_whole", "rl": "k_gemm_trailing", "ll": "k_gemm_trailing"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_queue_la_n16384_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_queue_whole_la_n16384_traffic.md")
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_counters_la_n16384.md")
 GEMM_SRC = os.path.join(ROOT, "paper_1611_06365_amd", "csrc", "gemm.hip")
 
 
@@ -82,6 +83,20 @@ def traffic_record():
     rec = json.loads(m.group(1))
     sha = hashlib.sha1(open(GEMM_SRC, "rb").read()).hexdigest()
     if rec.get("source_sha1") != sha:
+        return None
+    return rec
+
+
+def mfma_record():
+    """RU2's matrix-core busy fraction from the committed counter summary, or
+    None if missing or taken on a different kernel source."""
+    if not os.path.exists(MFMA_FILE):
+        return None
+    m = re.search(r"MFMA_JSON:\s*(\{.*\})", open(MFMA_FILE).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_sha1") != hashlib.sha1(open(GEMM_SRC, "rb").read()).hexdigest():
         return None
     return rec
 
@@ -636,6 +651,10 @@ def main() -> int:
         traffic = None
         if rec is not None:   # per traced launch: RU2 plus the helpers that join it
             traffic = rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]
+        mrec = mfma_record() if counted else None
+        busy = None
+        if mrec is not None and TRAFFIC_KERNEL[args.variant] in mrec.get("kernels", {}):
+            busy = mrec["kernels"][TRAFFIC_KERNEL[args.variant]]["mfma_busy_frac"]
         roof = {
             "bound": "mfma",
             "achieved": round(achieved, 3),
@@ -643,6 +662,10 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
             "traffic": traffic,
+            "mfma_busy_frac": busy,
+            "mfma_busy_note": "rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES per GRBM_GUI_ACTIVE cycle of the traced kernel "
+                              "over that of a calibration kernel with every matrix unit busy, per dispatch with "
+                              "dispatches serialized (profiles/mfma_counters_la_n16384.md)",
             "kernel": KERNEL_LABEL[args.variant],
             "launches": launches,
             "avg_launch_us": round(gemm_ms / launches * 1e3, 3),

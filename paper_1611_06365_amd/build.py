@@ -22,6 +22,25 @@ HIPCC_FLAGS = [
 ]
 
 
+CALIB_SRC = os.path.join(HERE, "calib", "mfma_peak.hip")
+CALIB_BIN = os.path.join(HERE, "calib", "mfma_peak")
+
+
+def build_calibration(verbose: bool = False) -> str:
+    """The matrix-core calibration program used by the counter profiles."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = CALIB_BIN + ".tmp"
+    cmd = ["hipcc", *flags, "-o", tmp, CALIB_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building the calibration program")
+    os.replace(tmp, CALIB_BIN)
+    return CALIB_BIN
+
+
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     tmp = LIB + ".tmp"
@@ -38,3 +57,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_calibration(verbose=True))

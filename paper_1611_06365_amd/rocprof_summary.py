@@ -15,6 +15,14 @@ come from them:
                                      traffic is N bytes read and N bytes written
   counters <dir> --kernel REGEX      mean of every collected counter per
                                      dispatch of the matching kernels
+  mfma --calib <dir> --run <dir> --kernel REGEX [--kernel REGEX ...]
+                                     matrix-core utilization of the matching
+                                     kernels: SQ_VALU_MFMA_BUSY_CYCLES per
+                                     GRBM_GUI_ACTIVE cycle of each, over the
+                                     same ratio for the calibration kernel
+                                     (k_mfma_peak, every SIMD's matrix unit
+                                     kept busy), and the FP64 flops per cycle
+                                     from SQ_INSTS_VALU_MFMA_MOPS_F64 (x 512)
 
 Run with `--output-format csv`; the CSV files are searched for under <dir>.
 """
@@ -120,6 +128,30 @@ def counters(d, kernel):
     return cnt, {k: v / max(cnt, 1) for k, v in acc.items()}
 
 
+def mfma(calib_dir, run_dir, kernels, calib_kernel="k_mfma_peak"):
+    """Utilization of the matrix units per kernel, normalized by the
+    calibration kernel's busy-cycle rate."""
+    n_c, cal = counters(calib_dir, calib_kernel)
+    if n_c == 0:
+        raise RuntimeError(f"no {calib_kernel} dispatch in {calib_dir}")
+    cal_rate = cal["SQ_VALU_MFMA_BUSY_CYCLES"] / cal["GRBM_GUI_ACTIVE"]
+    cal_fpc = 512.0 * cal["SQ_INSTS_VALU_MFMA_MOPS_F64"] / cal["GRBM_GUI_ACTIVE"]
+    out = {"calibration": {"kernel": calib_kernel, "dispatches": n_c,
+                           "mfma_busy_per_gui_cycle": round(cal_rate, 3),
+                           "f64_flops_per_gui_cycle": round(cal_fpc, 1)}, "kernels": {}}
+    for k in kernels:
+        n, m = counters(run_dir, k)
+        if n == 0 or not m.get("GRBM_GUI_ACTIVE"):
+            continue
+        rate = m["SQ_VALU_MFMA_BUSY_CYCLES"] / m["GRBM_GUI_ACTIVE"]
+        fpc = 512.0 * m.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) / m["GRBM_GUI_ACTIVE"]
+        out["kernels"][k] = {"dispatches": n, "mfma_busy_frac": round(rate / cal_rate, 4),
+                             "f64_flops_frac_of_calibration": round(fpc / cal_fpc, 4),
+                             "gui_active_cycles_per_dispatch": round(m["GRBM_GUI_ACTIVE"]),
+                             "mfma_mops_f64_per_dispatch": m.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)}
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -137,6 +169,10 @@ def main(argv=None) -> int:
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
+    mm = sub.add_parser("mfma")
+    mm.add_argument("--calib", required=True)
+    mm.add_argument("--run", required=True)
+    mm.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(f"{'kernel':72s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
@@ -147,6 +183,10 @@ def main(argv=None) -> int:
         for k, v in rec.items():
             print(f"{k}: {v}")
         print("TRAFFIC_JSON: " + json.dumps(rec))
+    elif a.cmd == "mfma":
+        rec = mfma(a.calib, a.run, a.kernel)
+        print(json.dumps(rec, indent=1))
+        print("MFMA_JSON: " + json.dumps(rec))
     else:
         n, means = counters(a.dir, a.kernel)
         print(f"dispatches matching {a.kernel}: {n}")

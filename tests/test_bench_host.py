@@ -36,3 +36,14 @@ def test_traffic_record_is_tied_to_the_gemm_source(tmp_path, monkeypatch):
     assert got == rec and got["fetch_bytes_per_step"] > 0 and got["write_bytes_per_step"] > 0
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
     assert bench.traffic_record() is None
+
+
+def test_mfma_record_is_tied_to_the_gemm_source(tmp_path, monkeypatch):
+    rec = bench.mfma_record()
+    assert rec is not None
+    frac = rec["kernels"]["k_gemm_queue_whole"]["mfma_busy_frac"]
+    assert 0.0 < frac <= 1.0
+    src = tmp_path / "gemm.hip"
+    src.write_bytes(b"// another kernel source\n")
+    monkeypatch.setattr(bench, "GEMM_SRC", str(src))
+    assert bench.mfma_record() is None
