@@ -289,12 +289,15 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         const int li = lane & 15, lq = lane >> 4;
         const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16, npair = nrb * nsb;
         T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
-        // each wave walks its 16 x 16 blocks with the next block's C loads
-        // issued before the current block's MFMAs (one block of prefetch)
+        // each wave walks its 16 x 16 blocks kG at a time, with the next kG
+        // blocks' C loads issued before the current ones' MFMAs: 2 kG blocks
+        // of loads in flight per wave cover the latency of the matrix's level
+        // of the memory hierarchy (a block is only 4 MFMA steps of work)
         constexpr int kWaves = kBT / kWave;
-        auto load_c = [&](int pp, acc_t& acc, int& rb, int& cb) {
-          rb = pp / nsb;
-          cb = (pp - rb * nsb) * 16 + li;
+        constexpr int kG = (sizeof(T) == 8 && NB == 32) ? 2 : 1;   // what the registers allow
+        auto load_c = [&](int pp, acc_t& acc) {
+          const int rb = pp / nsb;
+          const int cb = (pp - rb * nsb) * 16 + li;
           const int col = min(cb, cw - 1);   // a clamped lane is computed and not stored
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -302,28 +305,39 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
             acc[r] = C[(size_t)row * lda + col];
           }
         };
-        int pp = wave, rb = 0, cb = 0;
-        acc_t cur;
-        if (pp < npair) load_c(pp, cur, rb, cb);
+        acc_t cur[kG];
+        int pp = wave;
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+          if (pp + g * kWaves < npair) load_c(pp + g * kWaves, cur[g]);
         while (pp < npair) {
-          const int pn = pp + kWaves;
-          acc_t nxt;
-          int rbn = 0, cbn = 0;
-          if (pn < npair) load_c(pn, nxt, rbn, cbn);
-          const int arow = nb + min(rb * 16 + li, R - 1);
+          const int pn = pp + kG * kWaves;
+          acc_t nxt[kG];
 #pragma unroll
-          for (int s4 = 0; s4 < NB / 4; ++s4) {
-            const int k = 4 * s4 + lq;
-            cur = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + cb], cur);
+          for (int g = 0; g < kG; ++g)
+            if (pn + g * kWaves < npair) load_c(pn + g * kWaves, nxt[g]);
+#pragma unroll
+          for (int g = 0; g < kG; ++g) {
+            const int q = pp + g * kWaves;
+            if (q < npair) {
+              const int rb = q / nsb;
+              const int cb = (q - rb * nsb) * 16 + li;
+              const int arow = nb + min(rb * 16 + li, R - 1);
+              const int cbc = min(cb, cw - 1);
+#pragma unroll
+              for (int s4 = 0; s4 < NB / 4; ++s4) {
+                const int k = 4 * s4 + lq;
+                cur[g] = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + cbc], cur[g]);
+              }
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+                if (cb < cw && row < R) C[(size_t)row * lda + cb] = cur[g][r];
+              }
+            }
           }
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
-            if (cb < cw && row < R) C[(size_t)row * lda + cb] = cur[r];
-          }
-          cur = nxt;
-          rb = rbn;
-          cb = cbn;
+          for (int g = 0; g < kG; ++g) cur[g] = nxt[g];
           pp = pn;
         }
       }

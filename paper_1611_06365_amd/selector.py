@@ -91,18 +91,23 @@ def sizes(lo: int = 64, hi: int = 32768, count: int = 40) -> list[int]:
     return sorted(set(out))
 
 
+BATCH_MAX_ELEMS = 1 << 28   # largest batch timed: batch x n^2 <= 2^28 (2 GiB in FP64)
+
+
 def batch_grid() -> list[tuple[int, int]]:
-    """The batched training sweep: (order, batch count) pairs."""
+    """The batched training sweep: (order, batch count) pairs, up to
+    BATCH_MAX_ELEMS elements per batch."""
     ns = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
     bs = (16, 128, 1024, 8192, 20000)
-    return [(n, b) for n in ns for b in bs]
+    return [(n, b) for n in ns for b in bs if b * n * n <= BATCH_MAX_ELEMS]
 
 
 def held_out_shapes(seed: int = 7, singles: int = 24, batches: int = 24):
     """Shapes drawn outside the sweeps: orders log-uniform in [64, 32768]
     that are not multiples of 8 (the sweep's are), and batched (order, count)
     pairs with the order uniform in [9, 511] and the count log-uniform in
-    [20, 20000], avoiding the sweep's values."""
+    [20, 20000] (up to BATCH_MAX_ELEMS elements), avoiding the sweep's
+    values."""
     import numpy as np
 
     rng = np.random.default_rng(seed)
@@ -117,7 +122,7 @@ def held_out_shapes(seed: int = 7, singles: int = 24, batches: int = 24):
     while len(out_batch) < batches:
         n = int(rng.integers(9, 512))
         b = int(round(20 * 1000 ** rng.random()))
-        if (n, b) not in grid_b:
+        if (n, b) not in grid_b and b * n * n <= BATCH_MAX_ELEMS:
             out_batch.add((n, b))
     return sorted(out_single), sorted(out_batch)
 
