@@ -63,21 +63,27 @@ __device__ __forceinline__ void tile_coords(int wg, int tiles_m, int tiles_n, in
 __device__ __forceinline__ unsigned hw_xcc_id() { return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & 7u; }
 __device__ __forceinline__ unsigned hw_cu_id() { return (__builtin_amdgcn_s_getreg(4 | (0 << 6) | (31 << 11)) >> 8) & 15u; }
 
+// The tile's LDS stages; a kernel that runs several tile loops gives them the
+// same one.
+struct TileLds {
+  double As[2][BM * LDS_A];
+  double Bs[2][BK * LDS_B];
+};
+
 // One 128 x 128 tile of C := C - A B.  Ends with a workgroup barrier, so the
 // caller may start another tile at once.
 // CLAMP selects the edge-tile form: unconditional loads from clamped addresses
 // (the inner dimension masked as the stage goes to LDS; a C element outside
 // the matrix is loaded from a clamped address and never stored), so edge
 // loads stay in flight together; without it, edge loads are conditional, which
-// keeps the persistent kernel's registers (it never sees edges at the sizes it
-// serves) as they are.
+// keeps the registers of the general persistent kernel (k_gemm_queue) as they
+// are.
 template <bool VEC, bool CLAMP = false>
-__device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
-                                          int lda, const double* __restrict__ B, int ldb,
-                                          double* __restrict__ C, int ldc) {
-  __shared__ double As[2][BM * LDS_A];
-  __shared__ double Bs[2][BK * LDS_B];
-
+__device__ __forceinline__ void gemm_tile_in(TileLds& L, int tm, int tn, int m, int n, int k,
+                                             const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                             int ldb, double* __restrict__ C, int ldc) {
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   const int row0 = tm * BM, col0 = tn * BN;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -93,14 +99,14 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
   auto gload = [&](int k0) {
     const bool full = VEC && interior_mn && (k0 + BK <= k);
     if (full) {
-      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
-      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+      const dbl2_g* pa = reinterpret_cast<const dbl2_g*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const dbl2_g* pb = reinterpret_cast<const dbl2_g*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        double2 x = pa[e];
+        dbl2_g x = pa[e];
         ra[2 * e] = x.x;
         ra[2 * e + 1] = x.y;
-        double2 y = pb[e];
+        dbl2_g y = pb[e];
         rb[2 * e] = -y.x;
         rb[2 * e + 1] = -y.y;
       }
@@ -233,6 +239,14 @@ __device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, c
   }
 }
 
+template <bool VEC, bool CLAMP = false>
+__device__ __forceinline__ void gemm_tile(int tm, int tn, int m, int n, int k, const double* __restrict__ A,
+                                          int lda, const double* __restrict__ B, int ldb,
+                                          double* __restrict__ C, int ldc) {
+  __shared__ TileLds L;
+  gemm_tile_in<VEC, CLAMP>(L, tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
+}
+
 // The same 128 x 128 tile with the product in FP32: A and B are rounded to
 // FP32 as they are staged into LDS, v_mfma_f32_16x16x4f32 accumulates in FP32
 // over the whole inner dimension, and the epilogue subtracts the product from
@@ -292,14 +306,14 @@ __device__ __forceinline__ void gemm_tile_f32(int tm, int tn, int m, int n, int 
   auto gload = [&](int k0) {
     const bool full = VEC && interior_mn && (k0 + BK <= k);
     if (full) {
-      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
-      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+      const dbl2_g* pa = reinterpret_cast<const dbl2_g*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const dbl2_g* pb = reinterpret_cast<const dbl2_g*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        double2 x = pa[e];
+        dbl2_g x = pa[e];
         ra[2 * e] = x.x;
         ra[2 * e + 1] = x.y;
-        double2 y = pb[e];
+        dbl2_g y = pb[e];
         rb[2 * e] = y.x;
         rb[2 * e + 1] = y.y;
       }
@@ -401,14 +415,14 @@ __device__ __forceinline__ void gemm_tile_small(int tm, int tn, int m, int n, in
   auto gload = [&](int k0) {
     const bool full = VEC && interior_mn && (k0 + BK <= k);
     if (full) {
-      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
-      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+      const dbl2_g* pa = reinterpret_cast<const dbl2_g*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const dbl2_g* pb = reinterpret_cast<const dbl2_g*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        const double2 x = pa[e];
+        const dbl2_g x = pa[e];
         ra[2 * e] = x.x;
         ra[2 * e + 1] = x.y;
-        const double2 y = pb[e];
+        const dbl2_g y = pb[e];
         rb[2 * e] = -y.x;
         rb[2 * e + 1] = -y.y;
       }
@@ -524,14 +538,14 @@ __device__ __forceinline__ void gemm_tile_bf16(int tm, int tn, int m, int n, int
   auto gload = [&](int k0) {
     const bool full = VEC && interior_mn && (k0 + BK <= k);
     if (full) {
-      const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
-      const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
+      const dbl2_g* pa = reinterpret_cast<const dbl2_g*>(A + (size_t)(row0 + ar) * lda + k0 + ac);
+      const dbl2_g* pb = reinterpret_cast<const dbl2_g*>(B + (size_t)(k0 + br) * ldb + col0 + bc);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const double2 x = pa[e];
+        const dbl2_g x = pa[e];
         ra[2 * e] = x.x;
         ra[2 * e + 1] = x.y;
-        const double2 y = pb[e];
+        const dbl2_g y = pb[e];
         rb[2 * e] = y.x;
         rb[2 * e + 1] = y.y;
       }
@@ -645,10 +659,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_small(int m, int n, int k, cons
   gemm_tile_small<VEC>(tm, tn, m, n, k, A, lda, B, ldb, C, ldc);
 }
 
-// The FP64 persistent tile loop, pipelined across tiles, for launches whose
-// tiles and K stages are all whole (m and n multiples of 128, k of 16: the
-// look-ahead trailing updates at orders that are multiples of the block size,
-// with 16-byte aligned operands): the ticket of the
+// The FP64 persistent tile loop, pipelined across tiles, over the whole tiles
+// of a launch whose K stages are all whole (k a multiple of 16; the host
+// updates a partial last tile row and column with the tile kernels): the
+// ticket of the
 // next tile is taken while the current tile's first K stage runs (issued
 // before its products, resolved after them), the next tile's first K stage is
 // loaded while the current tile's last stage runs, and the epilogue stores each
@@ -657,12 +671,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_small(int m, int n, int k, cons
 // flight.  Each tile's arithmetic is that of gemm_tile (the same K stages, the
 // same MFMA order), so results do not depend on which workgroup took a tile.
 // `x` is the queue the workgroup draws from; only thread 0 uses it.
-__device__ __forceinline__ void queue_loop_f64_whole(int k, const double* __restrict__ A, int lda,
+template <bool VEC>
+__device__ __forceinline__ void queue_loop_f64_whole(TileLds& L, int k, const double* __restrict__ A, int lda,
                                                      const double* __restrict__ B, int ldb, double* __restrict__ C,
                                                      int ldc, int tiles_m, int tiles_n, unsigned* __restrict__ q,
                                                      int x) {
-  __shared__ double As[2][BM * LDS_A];
-  __shared__ double Bs[2][BK * LDS_B];
+  auto& As = L.As;
+  auto& Bs = L.Bs;
   __shared__ int s_next;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -683,18 +698,29 @@ __device__ __forceinline__ void queue_loop_f64_whole(int k, const double* __rest
   };
   double ra[8], rb[8];
   // stage k0 of the tile at (r0, c0) into registers, B negated (k is a
-  // multiple of 16: every stage is whole)
+  // multiple of 16: every stage is whole); 16-byte loads when the operands
+  // are 8-byte aligned, 8-byte ones otherwise
   auto gload = [&](int r0, int c0, int k0) {
-    const double2* pa = reinterpret_cast<const double2*>(A + (size_t)(r0 + ar) * lda + k0 + ac);
-    const double2* pb = reinterpret_cast<const double2*>(B + (size_t)(k0 + br) * ldb + c0 + bc);
+    const double* qa = A + (size_t)(r0 + ar) * lda + k0 + ac;
+    const double* qb = B + (size_t)(k0 + br) * ldb + c0 + bc;
+    if constexpr (VEC) {
+      const dbl2_g* pa = reinterpret_cast<const dbl2_g*>(qa);
+      const dbl2_g* pb = reinterpret_cast<const dbl2_g*>(qb);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const double2 xa = pa[e];
-      ra[2 * e] = xa.x;
-      ra[2 * e + 1] = xa.y;
-      const double2 yb = pb[e];
-      rb[2 * e] = -yb.x;
-      rb[2 * e + 1] = -yb.y;
+      for (int e = 0; e < 4; ++e) {
+        const dbl2_g xa = pa[e];
+        ra[2 * e] = xa.x;
+        ra[2 * e + 1] = xa.y;
+        const dbl2_g yb = pb[e];
+        rb[2 * e] = -yb.x;
+        rb[2 * e + 1] = -yb.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        ra[e] = qa[e];
+        rb[e] = -qb[e];
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -803,18 +829,21 @@ __device__ __forceinline__ void queue_loop_f64_whole(int k, const double* __rest
   }
 }
 
-// The persistent FP64 update when every tile and stage is whole and the
-// operands allow 16-byte loads (the host checks): the pipelined tile loop above, under
-// its own kernel name so that a kernel trace tells the two forms apart.
+// The persistent FP64 update over the whole tiles of a launch with whole K
+// stages (the host hands the partial last tile row and column to the tile
+// kernels): the pipelined tile loop above, under its own kernel name so that
+// a kernel trace tells the two forms apart.
+template <bool VEC>
 __global__ __launch_bounds__(256, 2) void k_gemm_queue_whole(int k, const double* __restrict__ A, int lda,
                                                              const double* __restrict__ B, int ldb,
                                                              double* __restrict__ C, int ldc, int tiles_m,
                                                              int tiles_n, unsigned* __restrict__ q,
                                                              unsigned* __restrict__ clear, int reserve) {
+  __shared__ TileLds L;
   const int tid = threadIdx.x;
   if (blockIdx.x == 0 && clear != nullptr && tid < kXcd) clear[tid * kQueueStride] = 0u;
   if (reserve > 0 && (int)(hw_cu_id() & 7u) < reserve) return;   // uniform over the workgroup
-  queue_loop_f64_whole(k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, q, (int)hw_xcc_id());
+  queue_loop_f64_whole<VEC>(L, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n, q, (int)hw_xcc_id());
 }
 
 // Persistent form for the look-ahead variant's RU2: queue x holds the logical
@@ -909,8 +938,7 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
   const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
   const long long tiles = (long long)tiles_m * tiles_n;
   if (tiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
-                   (lda % 2 == 0) && (ldb % 2 == 0);
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 8 == 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (trailing && traced) (void)trace_slot(m, n, k, &e0, &e1);
   if (e0) {
@@ -948,19 +976,23 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                       double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
-                      int prec, int* trace_id, int tail_of) {
+                      int prec, int* trace_id, int tail_of, bool edges) {
   if (trace_id != nullptr) *trace_id = -1;
   if (prec != kPrecF64 && prec != kPrecF32 && prec != kPrecBF16) return hipErrorInvalidValue;
   if (m <= 0 || n <= 0 || k <= 0) {
     if (clear == nullptr) return hipSuccess;
     m = n = k = 0;   // still clear the next slot
   }
-  const int tiles_m = (m + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+  // FP64 with whole K stages: the whole tiles go to the pipelined kernel, the
+  // partial last tile row and column (if any) to the tile kernels, after it
+  // and only with `edges` (the launch that owns the update, not its helpers)
+  const bool whole = prec == kPrecF64 && k % BK == 0 && m >= BM && n >= BN;
+  const int mi = whole ? m - m % BM : m, ni = whole ? n - n % BN : n;
+  const int tiles_m = (mi + BM - 1) / BM, tiles_n = (ni + BN - 1) / BN;
   const long long tiles = (long long)tiles_m * tiles_n;
   if (tiles > 0x7fffffffLL / kXcd) return hipErrorInvalidValue;
   if (reserve < 0 || reserve >= 8) return hipErrorInvalidValue;
-  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 16 == 0) &&
-                   (lda % 2 == 0) && (ldb % 2 == 0);
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) % 8 == 0);
   if (tiles == 0) {
     grid = 1;
     reserve = 0;
@@ -997,9 +1029,20 @@ hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int l
     else
       hipLaunchKernelGGL((k_gemm_queue<false, kPrecBF16>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,
                          ldc, tiles_m, tiles_n, q, clear, reserve);
-  } else if (vec && m % BM == 0 && n % BN == 0 && k % BK == 0) {
-    hipLaunchKernelGGL(k_gemm_queue_whole, dim3(grid), dim3(256), 0, s, k, A, lda, B, ldb, C, ldc, tiles_m, tiles_n,
-                       q, clear, reserve);
+  } else if (whole) {
+    if (vec)
+      hipLaunchKernelGGL(k_gemm_queue_whole<true>, dim3(grid), dim3(256), 0, s, k, A, lda, B, ldb, C, ldc, tiles_m,
+                         tiles_n, q, clear, reserve);
+    else
+      hipLaunchKernelGGL(k_gemm_queue_whole<false>, dim3(grid), dim3(256), 0, s, k, A, lda, B, ldb, C, ldc, tiles_m,
+                         tiles_n, q, clear, reserve);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && edges && mi < m)   // the last, partial tile row
+      e = gemm_update(s, m - mi, n, k, A + (size_t)mi * lda, lda, B, ldb, C + (size_t)mi * ldc, ldc, true,
+                      kPrecF64, false);
+    if (e == hipSuccess && edges && ni < n)   // the last, partial tile column above it
+      e = gemm_update(s, mi, n - ni, k, A, lda, B + ni, ldb, C + ni, ldc, true, kPrecF64, false);
+    if (e != hipSuccess) return e;
   } else {
     if (vec)
       hipLaunchKernelGGL((k_gemm_queue<true, kPrecF64>), dim3(grid), dim3(256), 0, s, m, n, k, A, lda, B, ldb, C,

@@ -246,7 +246,7 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false, c.prec, nullptr, tid));
+                         0, kLaHelpers, false, c.prec, nullptr, tid, /*edges=*/false));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
     } else {
@@ -374,7 +374,7 @@ hipError_t run_la_et(hipStream_t s0, const Ctx& c, int nb, EtWork* et, int force
       MLU_TRY(hipEventRecord(aux->width_ev, s1));
       MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
       MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false, c.prec, nullptr, tid));
+                         0, kLaHelpers, false, c.prec, nullptr, tid, /*edges=*/false));
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
       MLU_TRY(hipEventSynchronize(aux->width_ev));

@@ -7,6 +7,11 @@
 namespace mlu {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// Two consecutive doubles read from global memory with one 16-byte load at
+// any 8-byte aligned address (loads of several dwords need only dword
+// alignment on this hardware), so that rows of an odd leading dimension keep
+// the wide loads.
+typedef double dbl2_g __attribute__((ext_vector_type(2), aligned(8)));
 
 constexpr int kWave = 64;
 
@@ -119,10 +124,14 @@ hipError_t gemm_update(hipStream_t s, int m, int n, int k, const double* A, int 
 // `grid` 0 = two workgroups per CU.  `trace_id` (may be null) receives the
 // trace slot of a traced launch (-1 if none); `tail_of` >= 0 marks a helper
 // launch joining the queue of that traced launch, whose duration then extends
-// to the helpers' end if they joined before it ended.
+// to the helpers' end if they joined before it ended.  In FP64 with k a
+// multiple of 16 the queue holds the whole 128 x 128 tiles only, and the
+// partial last tile row and column are updated after them by the tile
+// kernels when `edges` is set: the launch that owns the update sets it, its
+// helpers (same m, n, k, hence the same queue) do not.
 hipError_t gemm_queue(hipStream_t s, int m, int n, int k, const double* A, int lda, const double* B, int ldb,
                       double* C, int ldc, unsigned* q, unsigned* clear, int reserve, int grid, bool traced,
-                      int prec = kPrecF64, int* trace_id = nullptr, int tail_of = -1);
+                      int prec = kPrecF64, int* trace_id = nullptr, int tail_of = -1, bool edges = true);
 hipError_t trace_begin(int capacity);
 hipError_t trace_end(int* launches, double* ms, double* flops, double* bytes);
 
@@ -154,10 +163,14 @@ hipError_t laswp(hipStream_t s, double* A, int lda, int m, int k1, int k2,
 hipError_t trsm_left(hipStream_t s, bool lower, bool unit, int nr, int ncols,
                      const double* T, int ldt, double* B, int ldb, const int32_t* skip = nullptr);
 
-// Inverses of the 256 x 256 diagonal blocks of the triangle of T (n x n):
-// Inv holds ceil(n/256) blocks of 256 x 256 (leading dimension 256), which
-// must hold identities (the leading nr x nr of each) on entry.
-constexpr int kInvBlock = 256;
+// Inverses of the kInvBlock x kInvBlock diagonal blocks of the triangle of T
+// (n x n): Inv holds ceil(n/kInvBlock) blocks of kInvBlock x kInvBlock
+// (leading dimension kInvBlock), which must hold identities (the leading
+// nr x nr of each) on entry.  The refinement applies the factors as GEMVs with
+// these inverses (each block's solve) and with the off-diagonal blocks (the
+// updates between them): 1024-row blocks keep that to 4 launches per 1024
+// rows and per factor.
+constexpr int kInvBlock = 1024;
 hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv);
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes);

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
 
   const int nblk = (nr + kDiag - 1) / kDiag;
   constexpr int kRB = (kRows / 16) / 4;   // 16-row blocks of the update per wave, at most
-  const bool t_vec = ((reinterpret_cast<uintptr_t>(T) & 15) == 0) && (ldt % 2 == 0);
+  const bool t_vec = (reinterpret_cast<uintptr_t>(T) & 7) == 0;
   // this thread's entry of T's diagonal block, loaded one step ahead
   const int dr = tid / kDiag, dc = tid % kDiag;
   auto diag_entry = [&](int step) {
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
   // (rows < nr, columns ib..ib+bs-1), and masked where they are used: a
   // select at issue would make every load wait for its own result.  A lane's
   // four entries of an item are contiguous (k = 4 lq .. 4 lq + 3), so a full
-  // block on 16-byte aligned rows takes them in two 16-byte loads.
+  // block takes them in two 16-byte loads.
   auto load_ta = [&](int step, double (&ta)[kRB][4]) {
     const int blk = LOWER ? step : nblk - 1 - step;
     const int ib = blk * kDiag;
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256, 2) void k_trsm_lds(int nr, int ncols, const do
 #pragma unroll
       for (int i = 0; i < kRB; ++i) {
         const int tr = min(rlo + (wave + 4 * i) * 16 + li, nr - 1);
-        const double2* pt = reinterpret_cast<const double2*>(T + (size_t)tr * ldt + ib + 4 * lq);
-        const double2 u0 = pt[0], u1 = pt[1];
+        const dbl2_g* pt = reinterpret_cast<const dbl2_g*>(T + (size_t)tr * ldt + ib + 4 * lq);
+        const dbl2_g u0 = pt[0], u1 = pt[1];
         ta[i][0] = u0.x;
         ta[i][1] = u0.y;
         ta[i][2] = u1.x;
@@ -211,6 +211,15 @@ hipError_t solve_block(hipStream_t s, bool lower, bool unit, int nr, int ncols, 
 
 hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv) {
   if (n <= 0) return hipSuccess;
+  if constexpr (kInvBlock != kRows) {   // each block's inverse solves T_kk X = I by the blocked solve
+    for (int r0 = 0; r0 < n; r0 += kInvBlock) {
+      const int nb = n - r0 < kInvBlock ? n - r0 : kInvBlock;
+      const hipError_t e = trsm_left(s, lower, unit, nb, nb, T + (size_t)r0 * ldt + r0, ldt,
+                                     Inv + (size_t)(r0 / kInvBlock) * kInvBlock * kInvBlock, kInvBlock);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int nblk = (n + kRows - 1) / kRows;
   const dim3 grid(kRows / kCols, nblk), block(256);
   const long long stride = (long long)kRows * kRows;

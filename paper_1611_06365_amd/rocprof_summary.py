@@ -6,6 +6,7 @@ come from them:
   stats   <dir>                      per-kernel calls / total ms / average us
                                      from a `--kernel-trace --stats` run
   traffic --fetch <dir> --write <dir> --kernel REGEX --copy-bytes N --source F
+          [--dispatches-per-step K]
                                      HBM bytes per dispatch of the kernels whose
                                      name matches REGEX, from two `--pmc` runs
                                      (FETCH_SIZE, then WRITE_SIZE, both in KiB
@@ -15,7 +16,15 @@ come from them:
                                      traffic is N bytes read and N bytes written
   counters <dir> --kernel REGEX      mean of every collected counter per
                                      dispatch of the matching kernels
-  mfma --calib <dir> --run <dir> --kernel REGEX [--kernel REGEX ...]
+  timeline <dir> --main REGEX [--iter I ...]
+                                     per outer iteration of the last traced
+                                     factorization (one dispatch of the
+                                     --main kernel on the caller's stream per
+                                     iteration): its duration, the period to
+                                     the next one, and the busy time and
+                                     kernels of the other streams in between;
+                                     with --iter, that iteration's kernels
+  mfma --calib <dir> --run <dir> --kernel REGEX [--kernel REGEX ...] [--source F]
                                      matrix-core utilization of the matching
                                      kernels: SQ_VALU_MFMA_BUSY_CYCLES per
                                      GRBM_GUI_ACTIVE cycle of each, over the
@@ -97,7 +106,7 @@ def _copy_dispatch(disp, counter, pattern):
     return best
 
 
-def traffic(fetch_dir, write_dir, kernel, copy_bytes, source, copy_kernel):
+def traffic(fetch_dir, write_dir, kernel, copy_bytes, source, copy_kernel, per_step=1):
     rec = {"kernel_regex": kernel, "copy_bytes": copy_bytes, "copy_kernel_regex": copy_kernel}
     for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         disp = per_dispatch(d)
@@ -113,6 +122,9 @@ def traffic(fetch_dir, write_dir, kernel, copy_bytes, source, copy_kernel):
         rec[f"{key}_copy_kib_raw"] = round(cval, 1)
         rec[f"{key}_scale"] = round(scale, 5)
         rec[f"{key}_bytes_per_launch"] = round(mean_kib * 1024.0 * scale)
+    rec["dispatches_per_step"] = per_step
+    rec["fetch_bytes_per_step"] = rec["fetch_bytes_per_launch"] * per_step
+    rec["write_bytes_per_step"] = rec["write_bytes_per_launch"] * per_step
     rec["source_sha1"] = hashlib.sha1(open(source, "rb").read()).hexdigest()
     return rec
 
@@ -126,6 +138,48 @@ def counters(d, kernel):
             for k, v in vals.items():
                 acc[k] += v
     return cnt, {k: v / max(cnt, 1) for k, v in acc.items()}
+
+
+def trace_rows(d: str):
+    """Kernel dispatches of a --kernel-trace run: dicts with name, queue,
+    start / end (ns) and grid size, sorted by start."""
+    rows = []
+    with open(_find(d, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append({"name": short_name(_col(r, "Kernel_Name")), "queue": _col(r, "Queue_Id"),
+                         "s": int(_col(r, "Start_Timestamp")), "e": int(_col(r, "End_Timestamp")),
+                         "grid": int(_col(r, "Grid_Size_X"))})
+    rows.sort(key=lambda r: r["s"])
+    return rows
+
+
+def timeline(d, main_regex, per_fact, min_grid, show):
+    rows = [r for r in trace_rows(d) if "mlu::" in r["name"]]
+    main = [r for r in rows if re.search(main_regex, r["name"]) and r["grid"] >= min_grid]
+    if len(main) < per_fact:
+        raise RuntimeError("fewer main dispatches than one factorization")
+    fac = main[-per_fact:]
+    mq = fac[0]["queue"]
+    print(f"{'iter':>4s} {'main_us':>8s} {'period_us':>9s} {'other_busy_us':>13s} {'other_kernels':>13s}")
+    total = 0.0
+    for i in range(len(fac) - 1):
+        a, b = fac[i], fac[i + 1]
+        other = [x for x in rows if x["queue"] != mq and a["s"] <= x["s"] < b["s"]]
+        busy = sum(x["e"] - x["s"] for x in other) / 1e3
+        total += (b["s"] - a["s"]) / 1e3
+        print(f"{i:4d} {(a['e'] - a['s']) / 1e3:8.0f} {(b['s'] - a['s']) / 1e3:9.0f} {busy:13.0f} {len(other):13d}")
+    print(f"sum of periods: {total / 1e3:.2f} ms")
+    for i in show:
+        a, b = fac[i], fac[i + 1]
+        per = defaultdict(lambda: [0, 0.0])
+        for x in rows:
+            if a["s"] <= x["s"] < b["s"]:
+                key = ("main" if x["queue"] == mq else "other", x["name"])
+                per[key][0] += 1
+                per[key][1] += (x["e"] - x["s"]) / 1e3
+        print(f"iteration {i}: stream, kernel, launches, total us")
+        for (q, k), (c, t) in sorted(per.items()):
+            print(f"  {q:5s} {k:40s} {c:4d} {t:9.1f}")
 
 
 def mfma(calib_dir, run_dir, kernels, calib_kernel="k_mfma_peak"):
@@ -164,27 +218,41 @@ def main(argv=None) -> int:
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--source", required=True)
+    t.add_argument("--dispatches-per-step", type=int, default=1,
+                   help="dispatches of the kernel per unit of the traced launch (RU2 and its helpers: 2)")
     t.add_argument("--copy-kernel", default=r"AUnaryFunctor<double, double, double, .*MulFunctor",
                    help="regex naming the calibration copy (bench.py --copy-calibration runs x * 1.0)")
     c = sub.add_parser("counters")
     c.add_argument("dir")
     c.add_argument("--kernel", required=True)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("dir")
+    tl.add_argument("--main", required=True, help="regex of the kernel launched once per iteration")
+    tl.add_argument("--per-factorization", type=int, default=62)
+    tl.add_argument("--min-grid", type=int, default=64 * 256 + 1,
+                    help="grid size (threads) above which a dispatch counts as the main one")
+    tl.add_argument("--iter", type=int, action="append", default=[])
     mm = sub.add_parser("mfma")
     mm.add_argument("--calib", required=True)
     mm.add_argument("--run", required=True)
     mm.add_argument("--kernel", action="append", required=True)
+    mm.add_argument("--source", default=None, help="kernel source whose sha1 the record carries")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(f"{'kernel':72s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
         for name, calls, tot, avg, pct in kernel_stats(a.dir)[: a.top]:
             print(f"{name:72s} {calls:7d} {tot / 1e6:10.3f} {avg / 1e3:10.3f} {pct:6.2f}")
     elif a.cmd == "traffic":
-        rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source, a.copy_kernel)
+        rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.source, a.copy_kernel, a.dispatches_per_step)
         for k, v in rec.items():
             print(f"{k}: {v}")
         print("TRAFFIC_JSON: " + json.dumps(rec))
+    elif a.cmd == "timeline":
+        timeline(a.dir, a.main, a.per_factorization, a.min_grid, a.iter)
     elif a.cmd == "mfma":
         rec = mfma(a.calib, a.run, a.kernel)
+        if a.source:
+            rec["source_sha1"] = hashlib.sha1(open(a.source, "rb").read()).hexdigest()
         print(json.dumps(rec, indent=1))
         print("MFMA_JSON: " + json.dumps(rec))
     else:

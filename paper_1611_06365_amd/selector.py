@@ -290,22 +290,29 @@ def regret_report(sel, recs, use_fallback=False):
     (regret 0) and are counted."""
     import numpy as np
 
-    regrets, deferred = [], 0
+    regrets, deferred, kinds, worst = [], 0, {"single": [], "batched": []}, None
     for (n, b, p), times in sorted(_by_shape(recs).items()):
         best = min(times.values())
         v, nb, fallback, _ = sel.choose_model(n, b, p)
         if use_fallback and fallback:
             deferred += 1
-            regrets.append(0.0)
-            continue
-        t = times.get((v, nb))
-        if t is None:
-            continue
-        regrets.append(t / best - 1.0)
+            r = 0.0
+        else:
+            t = times.get((v, nb))
+            if t is None:
+                continue
+            r = t / best - 1.0
+        regrets.append(r)
+        kinds["batched" if v == "batched" else "single"].append(r)
+        if worst is None or r > worst["regret"]:
+            bv, bnb = min(times, key=times.get)
+            worst = {"n": n, "batch": b, "precision": p, "chosen": [v, nb], "best": [bv, bnb], "regret": r}
     if not regrets:
         return None
     return {"cases": len(regrets), "mean_regret": float(np.mean(regrets)), "max_regret": float(np.max(regrets)),
-            "share_exact": float(np.mean([r == 0.0 for r in regrets])), "deferred_to_autotuner": deferred}
+            "share_exact": float(np.mean([r == 0.0 for r in regrets])), "deferred_to_autotuner": deferred,
+            "mean_regret_by_kind": {k: (float(np.mean(x)) if x else None) for k, x in kinds.items()},
+            "worst": worst}
 
 
 def train(recs, held=None, epochs=4000, seed=0, lr=3e-3):

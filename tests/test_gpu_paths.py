@@ -10,6 +10,8 @@
     edges in both dimensions), exact on integers and within the rounding bound
     on random inputs;
   * n = 3001 (a ragged last block) with nb = 32 and 64 against the C oracle;
+  * look-ahead at orders that are not multiples of the 128 x 128 tile, odd
+    leading dimensions among them: residual, |L| <= 1, legal interchanges;
   * look-ahead with early termination at n = 16384 for every stop mode:
     normwise residual <= 1e-13, |L| <= 1, legal interchanges, realized widths
     that cover the matrix;
@@ -206,6 +208,25 @@ def test_et_fullsize(force):
     print(f"et n={n} nb={nb} force={force}: {len(widths)} panels, residual {res:.2e}, max|L| {lmax:.3f}",
           flush=True)
     assert res <= 1e-13 and lmax <= 1.0
+    del F, A
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ LA at orders off the tile grid
+@pytest.mark.parametrize("n,recipe", [(8191, "uniform"), (9000, "spd"), (12289, "spd"), (12289, "uniform")])
+def test_la_orders_off_the_tile_grid(n, recipe):
+    """RU2 over the whole 128 x 128 tiles with the partial last tile row and
+    column after them (orders that are not multiples of 128), and 16-byte
+    loads from rows of an odd leading dimension: normwise residual, |L| <= 1,
+    legal interchanges (a uniform matrix pivots in most columns)."""
+    A = D.spd_bbt(n, seed=2, device=DEV) if recipe == "spd" else D.uniform01(n, seed=2, device=DEV)
+    F = A.clone()
+    ipiv, info = mlu.getrf(F, variant="la", nb=256, nb_inner=16)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    res, lmax = properties(A, F, ipiv)
+    print(f"la n={n} {recipe}: residual {res:.2e}, max|L| {lmax:.3f}", flush=True)
+    assert res <= (1e-13 if recipe == "spd" else 1e-12) and lmax <= 1.0
     del F, A
     torch.cuda.empty_cache()
 
