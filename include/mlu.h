@@ -264,12 +264,14 @@ int mlu_dsgesv_ir(void *stream, int n, int nrhs, const double *dA, int lda, cons
  *             gmres_tol * ||M^-1 r||_2, at max_krylov steps, or at a breakdown;
  *           solver MLU_IR_AUTO:  MLU_IR_LU while each correction at least
  *             halves berr, MLU_IR_GMRES from the first one that does not;
- *           x := x + d.
+ *           x := x + d;
+ *           stopping as not converged once berr is not finite or two GMRES
+ *           corrections in a row have each failed to halve it.
  *  dA (n x n, lda), db (n): read only.  dx (n): the solution.  d_ipiv and
  *  d_info as mlu_dgetrf, for the factors.  On return (the call waits for the
  *  stream once per outer and per GMRES step, so it is not capturable):
  *  *h_outer = corrections applied when berr <= tol was reached (0 if the first
- *  solve met it), or -1 if max_outer corrections did not reach it;
+ *  solve met it), or -1 if it stopped without reaching it;
  *  *h_inner = GMRES steps over all corrections; *h_berr = berr of the x
  *  returned.  1 <= max_krylov <= MLU_GMRES_MAX_KRYLOV; n <= 33280 (as
  *  mlu_dgetrf).

@@ -14,12 +14,16 @@
 //      row copied into LDS, one barrier, then every thread picks the winner,
 //      reads its row from LDS and updates its own row in registers;
 //   2. the panel's interchanges are applied to the columns outside it,
-//      gathered: each thread owns a column and loads every moved row before
+//      gathered: a lane pair owns a column and loads every moved row before
 //      storing any (no chain of dependent swaps);
 //   3. per 64 columns of A12: U12 := trilu(A11)^-1 A12 by forward
 //      substitution, eight threads per column; then A22 -= A21 U12 on the
 //      matrix cores (v_mfma 16 x 16 x 4 in the operand precision), 16 x 16
-//      blocks spread over the waves, A21 read from an LDS copy of the panel.
+//      blocks spread over the waves, A21 read from an LDS copy of the panel
+//      or, in FP64 with 32-column panels (two workgroups per CU instead of
+//      one), from global memory right after the panel was stored there.
+// Waves that hold no row of the current panel only take part in its
+// barriers.
 // Matrices are row-major (element (i, j) at A[i*lda + j]), in place.
 #include "mlu_internal.h"
 #include "../../include/mlu.h"
@@ -35,10 +39,20 @@ constexpr int kUC = 64;            // A12 columns staged per chunk
 constexpr int kMaxN = MLU_BATCH_MAX_N;
 constexpr int kBatchDefaultNB = 16;   // panel width when the caller passes 0
 
+// Whether the factored panel is kept in LDS for the trailing update (A21
+// read from there) or read back from global memory: LDS for every form but
+// FP64 with 32-column panels, whose 512 x 33 copy (135 KB) would leave room
+// for one workgroup per CU; without it that form holds two.
+template <typename T, int NB>
+constexpr bool panel_in_lds() {
+  return !(sizeof(T) == 8 && NB == 32);
+}
+
 template <typename T, int NB>
 struct BatchLds {
+  static constexpr bool kPL = panel_in_lds<T, NB>();
   static constexpr int kP = NB + 1;   // LDS pitch of the panel
-  T P[kMaxN * kP];         // the factored panel (L11\U11 over L21), rows 0 .. n-j-1
+  T P[kPL ? kMaxN * kP : NB * kP];    // the factored panel (L11\U11 over L21), or its diagonal block only
   T U[NB * kUC];           // U12 chunk
   T cand[2][kBT / kWave][NB];   // each wave's candidate pivot row, by column parity
   T wv[2][kBT / kWave];
@@ -132,9 +146,11 @@ template <typename T, int NB>
 __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, int32_t* __restrict__ ipiv,
                                            int32_t* __restrict__ info, BatchLds<T, NB>& L) {
   constexpr int kP = BatchLds<T, NB>::kP;
+  constexpr bool kPL = BatchLds<T, NB>::kPL;
   static_assert(kMaxN == kBT, "one panel row per thread");
   constexpr int kTG = kBT / kUC;     // threads per column in the solve for U12
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // scalar: LDS slots of the wave
   int zero_col = INT_MAX;
   for (int j = 0; j < n; j += NB) {
     const int nb = min(NB, n - j), rows = n - j;
@@ -152,6 +168,31 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     }
     int pos = r;
     bool live = r < rows;
+    if (wave * kWave >= rows) {
+      // a wave with no row of the panel takes part in the column steps'
+      // barriers only (the same count: the second one comes with a column of
+      // NaNs, known to every thread from LDS)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c < nb) {
+          const int par = c & 1;
+          if (lane == 0) {
+            L.wv[par][wave] = T(-1);
+            L.wr[par][wave] = INT_MAX;
+          }
+          __syncthreads();
+          T pm = L.wv[par][0];
+          int p = L.wr[par][0];
+#pragma unroll
+          for (int w = 1; w < kBT / kWave; ++w)
+            if (L.wv[par][w] > pm || (L.wv[par][w] == pm && L.wr[par][w] < p)) {
+              pm = L.wv[par][w];
+              p = L.wr[par][w];
+            }
+          if (__builtin_amdgcn_readfirstlane(p) >= rows) __syncthreads();
+        }
+      }
+    } else {
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       if (c < nb) {   // uniform: only the last panel is narrower
@@ -208,9 +249,8 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
           pos = p;
         }
         const T pv = prow[c];
-        if (pv == T(0)) {
-          if (j + c < zero_col) zero_col = j + c;   // same value in every thread
-        } else if (live) {
+        if (pv == T(0) && j + c < zero_col) zero_col = j + c;   // same value in every thread
+        if (pv != T(0) && live) {   // the division and rank-1 update
           const T l = v[c] / pv;
           v[c] = l;
 #pragma unroll
@@ -218,15 +258,19 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         }
       }
     }
-    // the factored panel to its final rows, in global and in LDS (A21 and
-    // trilu(A11) for step 3); src[t] := the panel-start position of the row
-    // now at position t
+    }
+    // the factored panel to its final rows, in global memory and in LDS
+    // (all of it, or, when step 3 reads A21 back from global memory, the
+    // diagonal block: the triangle of the solve for U12); src[t] := the
+    // panel-start position of the row now at position t
     if (r < rows) {
       T* a = A + (size_t)(j + pos) * lda + j;
 #pragma unroll
-      for (int cc = 0; cc < NB; ++cc) {
+      for (int cc = 0; cc < NB; ++cc)
         if (cc < nb) a[cc] = v[cc];
-        L.P[pos * kP + cc] = v[cc];
+      if (kPL || pos < NB) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) L.P[pos * kP + cc] = v[cc];
       }
       L.src[pos] = (int16_t)r;
     }
@@ -234,24 +278,26 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     if (tid < nb) ipiv[j + tid] = j + L.piv[tid] + 1;
     // 2. the interchanges outside the panel, gathered: the row at position t
     //    becomes the one from src[t] for t in {0..nb-1} and {piv[c]}; every
-    //    other row is unmoved.  A thread owns a column; all its loads are
-    //    issued before any of its stores (no order among the swaps remains).
+    //    other row is unmoved.  Two neighbouring lanes own a column, the even
+    //    one the targets 0..nb-1, the odd one the targets piv[c]; the code
+    //    between the loads and the stores has no branch, so both lanes' loads
+    //    (one instruction each) complete before either lane's first store:
+    //    no order among the swaps remains.
     bool any = false;
     for (int c = 0; c < nb; ++c) any |= L.piv[c] != c;
     if (any) {
-      for (int col = tid; col < n - nb; col += kBT) {
+      const int ncol = n - nb;
+      for (int idx = tid; idx < 2 * ncol; idx += kBT) {   // a lane pair is in range together
+        const int col = idx >> 1, h = idx & 1;
         const int g = col < j ? col : col + nb;
-        T st[2 * NB];
+        int tg[NB];
 #pragma unroll
-        for (int k = 0; k < 2 * NB; ++k) {
-          const int t = k < NB ? (k < nb ? k : 0) : (k - NB < nb ? L.piv[k - NB] : 0);
-          st[k] = A[(size_t)(j + L.src[t]) * lda + g];
-        }
+        for (int k = 0; k < NB; ++k) tg[k] = k < nb ? (h ? L.piv[k] : k) : 0;
+        T st[NB];
 #pragma unroll
-        for (int k = 0; k < 2 * NB; ++k) {
-          const int t = k < NB ? (k < nb ? k : 0) : (k - NB < nb ? L.piv[k - NB] : 0);
-          A[(size_t)(j + t) * lda + g] = st[k];   // every store to row t carries the same value
-        }
+        for (int k = 0; k < NB; ++k) st[k] = A[(size_t)(j + L.src[tg[k]]) * lda + g];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) A[(size_t)(j + tg[k]) * lda + g] = st[k];   // equal values to equal rows
       }
     }
     __syncthreads();   // P, and the interchanged columns, visible to the workgroup
@@ -284,17 +330,15 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         }
       }
       __syncthreads();
-      {
+      if constexpr (kPL) {
+        // A22 -= A21 U12 on the matrix cores, A21 from LDS: each wave walks
+        // its 16 x 16 blocks, with the next block's C loads issued before the
+        // current one's products
         typedef typename Mfma<T>::acc_t acc_t;
+        constexpr int kWaves = kBT / kWave;
         const int li = lane & 15, lq = lane >> 4;
         const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16, npair = nrb * nsb;
         T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
-        // each wave walks its 16 x 16 blocks kG at a time, with the next kG
-        // blocks' C loads issued before the current ones' MFMAs: 2 kG blocks
-        // of loads in flight per wave cover the latency of the matrix's level
-        // of the memory hierarchy (a block is only 4 MFMA steps of work)
-        constexpr int kWaves = kBT / kWave;
-        constexpr int kG = (sizeof(T) == 8 && NB == 32) ? 2 : 1;   // what the registers allow
         auto load_c = [&](int pp, acc_t& acc) {
           const int rb = pp / nsb;
           const int cb = (pp - rb * nsb) * 16 + li;
@@ -305,40 +349,71 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
             acc[r] = C[(size_t)row * lda + col];
           }
         };
-        acc_t cur[kG];
+        acc_t cur;
         int pp = wave;
-#pragma unroll
-        for (int g = 0; g < kG; ++g)
-          if (pp + g * kWaves < npair) load_c(pp + g * kWaves, cur[g]);
+        if (pp < npair) load_c(pp, cur);
         while (pp < npair) {
-          const int pn = pp + kG * kWaves;
-          acc_t nxt[kG];
+          const int pn = pp + kWaves;
+          acc_t nxt;
+          if (pn < npair) load_c(pn, nxt);
+          const int rb = pp / nsb;
+          const int cb = (pp - rb * nsb) * 16 + li;
+          const int arow = nb + min(rb * 16 + li, R - 1);
+          const int cbc = min(cb, cw - 1);
 #pragma unroll
-          for (int g = 0; g < kG; ++g)
-            if (pn + g * kWaves < npair) load_c(pn + g * kWaves, nxt[g]);
+          for (int s4 = 0; s4 < NB / 4; ++s4) {
+            const int k = 4 * s4 + lq;
+            cur = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + cbc], cur);
+          }
 #pragma unroll
-          for (int g = 0; g < kG; ++g) {
-            const int q = pp + g * kWaves;
-            if (q < npair) {
-              const int rb = q / nsb;
-              const int cb = (q - rb * nsb) * 16 + li;
-              const int arow = nb + min(rb * 16 + li, R - 1);
-              const int cbc = min(cb, cw - 1);
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+            if (cb < cw && row < R) C[(size_t)row * lda + cb] = cur[r];
+          }
+          cur = nxt;
+          pp = pn;
+        }
+      } else {
+        // A22 -= A21 U12 on the chunk, A21 from global memory: wave w takes the 16-row bands w, w + 8,
+        // ...; per band a lane loads its A21 fragments (element (16 rb + li,
+        // 4 s + lq), from the panel just stored, still in cache) once for all
+        // of the chunk's 16-column blocks, and every C load of the band is
+        // issued before the first product
+        typedef typename Mfma<T>::acc_t acc_t;
+        constexpr int kWaves = kBT / kWave, kSB = kUC / 16;
+        const int li = lane & 15, lq = lane >> 4;
+        const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16;
+        T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
+        const T* const A21 = A + (size_t)(j + nb) * lda + j;
+        for (int rb = wave; rb < nrb; rb += kWaves) {
+          const int arow = min(rb * 16 + li, R - 1);   // a clamped row is computed and not stored
+          T af[NB / 4];
 #pragma unroll
-              for (int s4 = 0; s4 < NB / 4; ++s4) {
-                const int k = 4 * s4 + lq;
-                cur[g] = Mfma<T>::run(L.P[arow * kP + k], -L.U[k * kUC + cbc], cur[g]);
-              }
+          for (int s4 = 0; s4 < NB / 4; ++s4) af[s4] = A21[(size_t)arow * lda + 4 * s4 + lq];
+          acc_t acc[kSB];
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int row = rb * 16 + Mfma<T>::row_of(lq, r);
-                if (cb < cw && row < R) C[(size_t)row * lda + cb] = cur[g][r];
-              }
+          for (int sb = 0; sb < kSB; ++sb) {
+            const int col = min(sb * 16 + li, cw - 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = min(rb * 16 + Mfma<T>::row_of(lq, r), R - 1);
+              acc[sb][r] = sb < nsb ? C[(size_t)row * lda + col] : T(0);
             }
           }
 #pragma unroll
-          for (int g = 0; g < kG; ++g) cur[g] = nxt[g];
-          pp = pn;
+          for (int sb = 0; sb < kSB; ++sb) {
+            if (sb < nsb) {
+              const int col = min(sb * 16 + li, cw - 1);
+#pragma unroll
+              for (int s4 = 0; s4 < NB / 4; ++s4)
+                acc[sb] = Mfma<T>::run(af[s4], -L.U[(4 * s4 + lq) * kUC + col], acc[sb]);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+                if (sb * 16 + li < cw && row < R) C[(size_t)row * lda + sb * 16 + li] = acc[sb][r];
+              }
+            }
+          }
         }
       }
       __syncthreads();
@@ -375,12 +450,13 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int32_t* 
 }
 
 // Waves per SIMD each instantiation is built for, i.e. resident workgroups
-// per CU (as many as the LDS allows) x 8 waves / 4 SIMDs: FP64 16 -> 2
-// workgroups, FP64 32 -> 1, FP32 16 -> 3, FP32 32 -> 2.  Registers are held to
-// it (the second launch bound is the minimum waves per execution unit).
+// per CU x 8 waves / 4 SIMDs: two workgroups per CU, three for FP32 with
+// 16-column panels (so that one matrix's panel, a latency chain, runs beside
+// another's work).  Registers are held to it (the second launch bound is the
+// minimum waves per execution unit).
 template <typename T, int NB>
 constexpr int batched_min_blocks() {
-  return (sizeof(T) == 8 ? (NB == 16 ? 2 : 1) : (NB == 16 ? 3 : 2)) * (kBT / kWave) / 4;
+  return (sizeof(T) == 4 && NB == 16 ? 3 : 2) * (kBT / kWave) / 4;
 }
 
 template <typename T, int NB>

@@ -35,6 +35,9 @@ struct IrState {
 // grown past this factor times the smallest one reached (the corrections then
 // diverge: kappa(A) u_low is too large for plain refinement).
 constexpr double kDivergeFactor = 2.0;
+// GMRES-IR gives up after this many GMRES corrections in a row that each fail
+// to halve the backward error.
+constexpr int kGmresStalls = 2;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
@@ -654,8 +657,9 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
 
   const unsigned gc = (unsigned)((n + 255) / 256);
   bool gmres_mode = solver == MLU_IR_GMRES;
+  bool last_gmres = false;   // the correction just applied was a GMRES one
   double prev_berr = 0.0, best_berr = 0.0;
-  int inner = 0;
+  int inner = 0, stalled = 0;
   GmresState hs{};
   for (int it = 0;; ++it) {
     // r := b - A x and the backward error of x
@@ -681,7 +685,15 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
       return 0;
     }
     if (solver == MLU_IR_AUTO && !gmres_mode && it > 0 && !(hs.berr <= 0.5 * prev_berr)) gmres_mode = true;
+    // GMRES corrections that stall: two in a row that do not halve berr end
+    // the solve (the preconditioner is too poor for this matrix)
+    if (last_gmres) stalled = hs.berr <= 0.5 * prev_berr ? 0 : stalled + 1;
+    if (stalled >= kGmresStalls || !std::isfinite(hs.berr)) {
+      *h_outer = -1;
+      return 0;
+    }
     prev_berr = hs.berr;
+    last_gmres = gmres_mode;
     // z := M^-1 r, into the first basis vector
     hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, R, 1, V, 1, nullptr);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;

@@ -108,6 +108,22 @@ def test_lu_ir_stalls_where_gmres_ir_converges():
     assert outer_a >= 1 and inner_a >= 1 and be_a <= 1e-13
 
 
+def test_gmres_ir_gives_up_when_its_corrections_stall():
+    """GMRES corrections limited to one Krylov step on BF16 factors at
+    kappa = 1e8 cannot reach the target: the solve stops as not converged
+    after two GMRES corrections in a row that fail to halve berr, long before
+    max_outer."""
+    n, cond, max_outer = 800, 1e8, 40
+    A = G.haar_spectrum(n, cond, seed=9)
+    b = G.gaussian_rhs(n, 1, seed=9)[:, 0]
+    x, info, outer, inner, be = solve(A, b, precision="bf16", solver="gmres", tol=1e-13, max_outer=max_outer,
+                                      max_krylov=1, gmres_tol=1e-6, nb=64)
+    print(f"bf16 cond 1e8, one Krylov step per correction: outer {outer}, inner {inner}, berr {be:.2e}",
+          flush=True)
+    assert info == 0 and outer == -1 and be > 1e-13
+    assert 2 <= inner < max_outer
+
+
 def test_auto_stays_lu_ir_when_it_converges():
     A = G.haar_spectrum(400, 1e2, seed=4)
     b = G.gaussian_rhs(400, 1, seed=5)[:, 0]
