@@ -190,22 +190,24 @@ __global__ void k_gather(int n, const int32_t* __restrict__ perm, const double* 
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) Out[i] = X[perm[i]];
 }
 
-// leading nr x nr of every 256 x 256 block := identity, the rest zero
-__global__ void k_identity_blocks(int n, double* __restrict__ Inv) {
-  const int nblk = (n + kInvBlock - 1) / kInvBlock;
-  const size_t total = (size_t)nblk * kInvBlock * kInvBlock;
+// every ib x ib block := identity
+__global__ void k_identity_blocks(int n, int ib, double* __restrict__ Inv) {
+  const int nblk = (n + ib - 1) / ib;
+  const size_t total = (size_t)nblk * ib * ib;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = (e / kInvBlock) % kInvBlock, c = e % kInvBlock;
+    const size_t r = (e / ib) % ib, c = e % ib;
     Inv[e] = r == c ? 1.0 : 0.0;
   }
 }
 
-// B := U^-1 L^-1 P B with the inverted diagonal blocks (Linv, Uinv): per
-// 256-row block a GEMV with the block's inverse, then a GEMV update of the
+size_t inv_bytes(int n, int ib) { return (size_t)((n + ib - 1) / ib) * ib * ib * sizeof(double); }
+
+// B := U^-1 L^-1 P B with the inverted ib x ib diagonal blocks (Linv, Uinv):
+// per block row a GEMV with the block's inverse, then a GEMV update of the
 // rows still to be solved.  tmp: n x nrhs (leading dimension nrhs).
 // perm / ybuf (optional, one right-hand side): P is applied by a gather of B
 // into ybuf through perm (k_perm_from_ipiv) instead of interchanges in place.
-hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int ld, const int32_t* ipiv,
+hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int ld, const int32_t* ipiv, int ib,
                          const double* Linv, const double* Uinv, double* Bx, int ldb, double* tmp,
                          const int32_t* skip, const int32_t* perm = nullptr, double* ybuf = nullptr) {
   double* Y = Bx;
@@ -218,19 +220,19 @@ hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int l
   } else if (laswp(s, Bx, ldb, n, 0, n, ipiv, 0, nrhs, 0, 0, nullptr, skip) != hipSuccess) {
     return hipErrorUnknown;
   }
-  const int nblk = (n + kInvBlock - 1) / kInvBlock;
-  const size_t bsz = (size_t)kInvBlock * kInvBlock;
+  const int nblk = (n + ib - 1) / ib;
+  const size_t bsz = (size_t)ib * ib;
   for (int k = 0; k < nblk; ++k) {   // L: y := P B (in place), x_k = Linv_k y_k -> tmp
-    const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
-    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Linv + k * bsz, kInvBlock, Y + (size_t)r0 * ldy, ldy, nullptr, 0,
+    const int r0 = k * ib, nbk = min(ib, n - r0);
+    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Linv + k * bsz, ib, Y + (size_t)r0 * ldy, ldy, nullptr, 0,
                     tmp + (size_t)r0 * nrhs, nrhs, skip));
     if (r0 + nbk < n)
       MLU_IR_TRY(gemv(s, n - r0 - nbk, nbk, nrhs, LU + (size_t)(r0 + nbk) * ld + r0, ld, tmp + (size_t)r0 * nrhs,
                       nrhs, Y + (size_t)(r0 + nbk) * ldy, ldy, Y + (size_t)(r0 + nbk) * ldy, ldy, skip));
   }
   for (int k = nblk - 1; k >= 0; --k) {   // U: z := tmp (in place), x_k = Uinv_k z_k -> B
-    const int r0 = k * kInvBlock, nbk = min(kInvBlock, n - r0);
-    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Uinv + k * bsz, kInvBlock, tmp + (size_t)r0 * nrhs, nrhs, nullptr, 0,
+    const int r0 = k * ib, nbk = min(ib, n - r0);
+    MLU_IR_TRY(gemv(s, nbk, nbk, nrhs, Uinv + k * bsz, ib, tmp + (size_t)r0 * nrhs, nrhs, nullptr, 0,
                     Bx + (size_t)r0 * ldb, ldb, skip));
     if (r0 > 0)
       MLU_IR_TRY(gemv(s, r0, nbk, nrhs, LU + r0, ld, Bx + (size_t)r0 * ldb, ldb, tmp, nrhs, tmp, nrhs, skip));
@@ -285,7 +287,7 @@ struct IrLayout {
 };
 IrLayout ir_layout(int n, int nrhs) {
   IrLayout L;
-  const size_t inv = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(double);
+  const size_t inv = inv_bytes(n, kIrInvBlock);
   L.lu = align_up(workspace_bytes());
   L.linv = align_up(L.lu + (size_t)n * n * sizeof(double));
   L.uinv = align_up(L.linv + inv);
@@ -433,7 +435,7 @@ struct GmresLayout {
 };
 GmresLayout gmres_layout(int n, int m) {
   GmresLayout L;
-  const size_t inv = (size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock * sizeof(double);
+  const size_t inv = inv_bytes(n, kGmresInvBlock);
   const size_t vec = (size_t)n * sizeof(double), small = (size_t)(m + 2) * sizeof(double);
   L.lu = align_up(workspace_bytes());
   L.linv = align_up(L.lu + (size_t)n * n * sizeof(double));
@@ -524,17 +526,18 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
   if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
   // inverses of the factors' 256 x 256 diagonal blocks (the solves below are
   // then GEMVs), the norms of A and B, then x := (LU)^-1 P b
-  const unsigned gi = grid_for((size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock);
-  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Linv);
-  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Uinv);
+  const unsigned gi = grid_for(inv_bytes(n, kIrInvBlock) / sizeof(double));
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, kIrInvBlock, Linv);
+  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, kIrInvBlock, Uinv);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  if (invert_diag_blocks(s, true, true, n, LU, n, Linv) != hipSuccess) return MLU_ERR_HIP;
-  if (invert_diag_blocks(s, false, false, n, LU, n, Uinv) != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, true, true, n, LU, n, Linv, kIrInvBlock) != hipSuccess) return MLU_ERR_HIP;
+  if (invert_diag_blocks(s, false, false, n, LU, n, Uinv, kIrInvBlock) != hipSuccess) return MLU_ERR_HIP;
   hipLaunchKernelGGL(k_ir_anorm, dim3(gw), dim3(256), 0, s, n, dA, lda, &st->anorm);
   hipLaunchKernelGGL(k_ir_colmax, dim3(gr), dim3(256), 0, s, n, nrhs, dB, ldb, bnorm, nullptr);
   hipLaunchKernelGGL(k_ir_copy, dim3(gr), dim3(256), 0, s, n, nrhs, dB, ldb, dX, ldx, nullptr);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, Linv, Uinv, dX, ldx, T, nullptr) != hipSuccess) return MLU_ERR_HIP;
+  if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, kIrInvBlock, Linv, Uinv, dX, ldx, T, nullptr) != hipSuccess)
+    return MLU_ERR_HIP;
   // refinement: residual and stop test, then a correction, until converged
   for (int it = 0; it <= max_iter; ++it) {
     if (gemv(s, n, n, nrhs, dA, lda, dX, ldx, dB, ldb, R, nrhs, done) != hipSuccess) return MLU_ERR_HIP;
@@ -544,7 +547,8 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
                        d_iters, d_berr);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
     if (it == max_iter) break;
-    if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, Linv, Uinv, R, nrhs, T, done) != hipSuccess) return MLU_ERR_HIP;
+    if (getrs_blocked(s, n, nrhs, LU, n, d_ipiv, kIrInvBlock, Linv, Uinv, R, nrhs, T, done) != hipSuccess)
+      return MLU_ERR_HIP;
     hipLaunchKernelGGL(k_ir_axpy, dim3(gr), dim3(256), 0, s, n, nrhs, R, nrhs, dX, ldx, done);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   }
@@ -638,12 +642,21 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   const int rc = getrf_entry(stream, n, n, LU, n, d_ipiv, d_info, variant, nb, nb_inner, MLU_RL, precision, nullptr, 0, -1,
                              d_work, work_bytes, 0);
   if (rc != 0) return rc == MLU_ERR_HIP ? rc : MLU_ERR_HIP;
-  const unsigned gi = grid_for((size_t)((n + kInvBlock - 1) / kInvBlock) * kInvBlock * kInvBlock);
-  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Linv);
-  hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, Uinv);
-  if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  if (invert_diag_blocks(s, true, true, n, LU, n, Linv) != hipSuccess) return MLU_ERR_HIP;
-  if (invert_diag_blocks(s, false, false, n, LU, n, Uinv) != hipSuccess) return MLU_ERR_HIP;
+  // the inverted diagonal blocks of the factors: those of mlu_dsgesv_ir for
+  // plain corrections (the same arithmetic step for step), the larger ones
+  // from the first GMRES correction on (built when it comes)
+  int ib = 0;
+  const auto invert = [&](int blk) -> int {
+    ib = blk;
+    const unsigned gi = grid_for(inv_bytes(n, ib) / sizeof(double));
+    hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, ib, Linv);
+    hipLaunchKernelGGL(k_identity_blocks, dim3(gi), dim3(256), 0, s, n, ib, Uinv);
+    if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    if (invert_diag_blocks(s, true, true, n, LU, n, Linv, ib) != hipSuccess) return MLU_ERR_HIP;
+    if (invert_diag_blocks(s, false, false, n, LU, n, Uinv, ib) != hipSuccess) return MLU_ERR_HIP;
+    return 0;
+  };
+  if (invert(solver == MLU_IR_GMRES ? kGmresInvBlock : kIrInvBlock) != 0) return MLU_ERR_HIP;
   hipLaunchKernelGGL(k_ir_anorm, dim3(gw), dim3(256), 0, s, n, dA, lda, &st->anorm);
   hipLaunchKernelGGL(k_ir_colmax, dim3(g1), dim3(256), 0, s, n, 1, db, 1, &st->bnorm, nullptr);
   hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, db, 1, dx, 1, nullptr);
@@ -651,7 +664,7 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(256), 0, s, n, d_ipiv, perm);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   const auto precondition = [&](double* v) {   // v := M^-1 v
-    return getrs_blocked(s, n, 1, LU, n, d_ipiv, Linv, Uinv, v, 1, T, nullptr, perm, Yb);
+    return getrs_blocked(s, n, 1, LU, n, d_ipiv, ib, Linv, Uinv, v, 1, T, nullptr, perm, Yb);
   };
   if (precondition(dx) != hipSuccess) return MLU_ERR_HIP;
 
@@ -694,6 +707,7 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
     }
     prev_berr = hs.berr;
     last_gmres = gmres_mode;
+    if (gmres_mode && ib != kGmresInvBlock && invert(kGmresInvBlock) != 0) return MLU_ERR_HIP;
     // z := M^-1 r, into the first basis vector
     hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, R, 1, V, 1, nullptr);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;

@@ -163,15 +163,21 @@ hipError_t laswp(hipStream_t s, double* A, int lda, int m, int k1, int k2,
 hipError_t trsm_left(hipStream_t s, bool lower, bool unit, int nr, int ncols,
                      const double* T, int ldt, double* B, int ldb, const int32_t* skip = nullptr);
 
-// Inverses of the kInvBlock x kInvBlock diagonal blocks of the triangle of T
-// (n x n): Inv holds ceil(n/kInvBlock) blocks of kInvBlock x kInvBlock
-// (leading dimension kInvBlock), which must hold identities (the leading
-// nr x nr of each) on entry.  The refinement applies the factors as GEMVs with
-// these inverses (each block's solve) and with the off-diagonal blocks (the
-// updates between them): 1024-row blocks keep that to 4 launches per 1024
-// rows and per factor.
-constexpr int kInvBlock = 1024;
-hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv);
+// Inverses of the ib x ib diagonal blocks of the triangle of T (n x n): Inv
+// holds ceil(n/ib) blocks of ib x ib (leading dimension ib), which must hold
+// identities (the leading nr x nr of each) on entry.  The refinement applies
+// the factors as GEMVs with these inverses (each block's solve) and with the
+// off-diagonal blocks (the updates between them), 4 launches per block row
+// and per pair of factors.  ib = 256 takes one batched triangular-solve
+// launch per triangle; larger blocks solve each block on its own (ib^2 / 3
+// flops per row, far more time) and save launches in every later
+// application.  Plain refinement applies the factors a few times and uses
+// 256; GMRES-IR applies them once per Krylov step and uses 1024 (256 when it
+// makes plain corrections only, as mlu_dsgesv_ir).
+constexpr int kIrInvBlock = 256;
+constexpr int kGmresInvBlock = 1024;
+hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv,
+                              int ib);
 
 hipError_t zero_bytes(hipStream_t s, void* p, size_t bytes);
 

@@ -209,13 +209,15 @@ hipError_t solve_block(hipStream_t s, bool lower, bool unit, int nr, int ncols, 
 
 }  // namespace
 
-hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv) {
+hipError_t invert_diag_blocks(hipStream_t s, bool lower, bool unit, int n, const double* T, int ldt, double* Inv,
+                              int ib) {
   if (n <= 0) return hipSuccess;
-  if constexpr (kInvBlock != kRows) {   // each block's inverse solves T_kk X = I by the blocked solve
-    for (int r0 = 0; r0 < n; r0 += kInvBlock) {
-      const int nb = n - r0 < kInvBlock ? n - r0 : kInvBlock;
+  if (ib < 1) return hipErrorInvalidValue;
+  if (ib != kRows) {   // each block's inverse solves T_kk X = I by the blocked solve
+    for (int r0 = 0; r0 < n; r0 += ib) {
+      const int nb = n - r0 < ib ? n - r0 : ib;
       const hipError_t e = trsm_left(s, lower, unit, nb, nb, T + (size_t)r0 * ldt + r0, ldt,
-                                     Inv + (size_t)(r0 / kInvBlock) * kInvBlock * kInvBlock, kInvBlock);
+                                     Inv + (size_t)(r0 / ib) * ib * ib, ib);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
