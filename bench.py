@@ -308,6 +308,41 @@ def et_section(args, A, ipiv, info, work):
             "n": A.shape[0], "matrix": args.matrix, "rows": rows}
 
 
+def ws_section(args, A, ipiv, info, work):
+    """Worker sharing on and off (the comparison of the paper's Section 5.2):
+    look-ahead (mlu_dgetrf, LA: the panel's workgroups join RU2's tile queue
+    once PF3 is done) against MLU_LA_NOWS (they idle after PF3), on the bench
+    matrix; the best of three runs after a warm-up, each on a fresh copy."""
+    import torch
+
+    from paper_1611_06365_amd import mlu
+
+    M = torch.empty_like(A)
+
+    def timed(variant, reps=3):
+        best = None
+        for _ in range(reps + 1):   # the first is a warm-up
+            M.copy_(A)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mlu.getrf(M, variant=variant, nb=args.nb, nb_inner=args.nb_inner, ipiv=ipiv, info=info, work=work)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best, int(info.item())
+
+    t_ws, i_ws = timed("la")
+    t_no, i_no = timed("la_nows")
+    del M
+    out = {"what": "look-ahead with worker sharing (LA) vs without (the panel stream idles after PF3)",
+           "n": A.shape[0], "nb": args.nb, "matrix": args.matrix, "ms_la": round(t_ws, 3),
+           "ms_la_without_worker_sharing": round(t_no, 3), "gain": round(t_no / t_ws, 4), "info": [i_ws, i_no]}
+    log(f"worker sharing: {out}")
+    return out
+
+
 def lead_schedule(n: int, nb: int):
     """Blocks of 2 nb over the first 3/8 of the order (then nb)."""
     return [2 * nb] * max(1, (3 * n // 8) // (2 * nb))
@@ -556,6 +591,7 @@ def main() -> int:
     ap.add_argument("--max-krylov", type=int, default=200, help="GMRES-IR Krylov dimension limit")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-LU measurement")
     ap.add_argument("--no-et", action="store_true", help="skip the early-termination comparison")
+    ap.add_argument("--no-ws", action="store_true", help="skip the worker-sharing on / off comparison")
     ap.add_argument("--no-schedule", action="store_true", help="skip the per-iteration block-size comparison")
     ap.add_argument("--lead-schedule", action="store_true",
                     help="time the main step with blocks of 2*nb over the first 3/8 of the order, then nb "
@@ -689,6 +725,10 @@ def main() -> int:
     if not args.no_et:
         et = et_section(args, A, ipiv, info, work)
 
+    ws = None
+    if not args.no_ws and args.variant == "la":
+        ws = ws_section(args, A, ipiv, info, work)
+
     blocks = None
     if not args.no_schedule:
         blocks = schedule_section(args, A, ipiv, info, work)
@@ -741,6 +781,7 @@ def main() -> int:
         "uniform01": uniform,
         "mixed": mixed,
         "early_termination": et,
+        "worker_sharing": ws,
         "block_schedule": blocks,
         "selector": sel,
         "grid": grid,

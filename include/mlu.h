@@ -50,7 +50,12 @@ extern "C" {
 enum mlu_variant {
   MLU_RL = 0, /* blocked right-looking: RL1 panel, RL2 trsm, RL3 gemm                 */
   MLU_LL = 1, /* blocked left-looking: LL1 trsm, LL2 gemm, LL3 panel (lazy swaps)     */
-  MLU_LA = 2  /* right-looking with look-ahead: T_PF (PF1-PF3) || T_RU (RU1-RU2)      */
+  MLU_LA = 2, /* right-looking with look-ahead: T_PF (PF1-PF3) || T_RU (RU1-RU2), the  */
+              /* panel's workgroups joining RU2 once PF3 is done (worker sharing,     */
+              /* Section 4.1)                                                         */
+  /* 3 is the batched kernel in mlu_select's answers, not a variant here */
+  MLU_LA_NOWS = 4 /* MLU_LA without worker sharing: T_PF idles after PF3 (the      */
+                  /* comparison of Section 5.2); same arithmetic, bitwise results */
 };
 
 /*
@@ -118,7 +123,7 @@ int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t
  *              kernel holds).
  *  d_ipiv      device int32[min(m, n)].
  *  d_info      device int32[1].
- *  variant     MLU_RL, MLU_LL or MLU_LA.
+ *  variant     MLU_RL, MLU_LL, MLU_LA or MLU_LA_NOWS.
  *  nb          outer block size b (>= 1); nb = 1 gives each variant's
  *              unblocked form, nb >= min(m,n) a single panel.
  *  nb_inner    block size b_i of the panel factorization, 0..32 (0 = min(nb,

@@ -132,6 +132,7 @@ struct Ctx {
   int prec;          // product precision of the outer trailing updates
   unsigned* epoch;   // panel launch counter of this call (panels run one at a time)
   int inner;         // algorithm of the panel factorization: MLU_RL or MLU_LL
+  bool sharing = true;   // look-ahead: the panel's workgroups join RU2 after PF3
   double* at(int i, int j) const { return A + (size_t)i * lda + j; }
 };
 
@@ -235,7 +236,7 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       unsigned* next = c.queue->ctr[(k + 2) % kQueueSlots];
       if (c0 < c.n) MLU_TRY(trsm_left(s0, true, true, b, c.n - c0, c.at(j, j), c.lda, c.at(j, c0), c.lda));
       MLU_TRY(hipEventRecord(aux->ru1, s0));
-      // T_PF: PF1, PF2, PF3, then it joins RU2's queue (after RU1 is done)
+      // T_PF: PF1, PF2, PF3, then (worker sharing) it joins RU2's queue once RU1 is done
       MLU_TRY(hipStreamWaitEvent(s1, aux->fork, 0));
       MLU_TRY(update_cols(s1, c, j, b, jn, jn + bp, /*traced=*/false));         // PF1, PF2
       MLU_TRY(hipEventRecord(aux->pf2, s1));
@@ -244,9 +245,11 @@ hipError_t run_la(hipStream_t s0, const Ctx& c, const std::vector<int>& sched, i
       MLU_TRY(gemm_queue(s0, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, next,
                          kLaReserve, 0, true, c.prec, &tid));
       MLU_TRY(factor_panel(s1, c, jn, bp));                                      // PF3
-      MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
-      MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q, nullptr,
-                         0, kLaHelpers, false, c.prec, nullptr, tid, /*edges=*/false));
+      if (c.sharing) {
+        MLU_TRY(hipStreamWaitEvent(s1, aux->ru1, 0));
+        MLU_TRY(gemm_queue(s1, mr, nr, b, c.at(jn, j), c.lda, c.at(j, c0), c.lda, c.at(jn, c0), c.lda, q,
+                           nullptr, 0, kLaHelpers, false, c.prec, nullptr, tid, /*edges=*/false));
+      }
       MLU_TRY(hipEventRecord(aux->join, s1));
       MLU_TRY(hipStreamWaitEvent(s0, aux->join, 0));
     } else {
@@ -456,7 +459,7 @@ int mlu_init(void) {
 int mlu_dgetrf_workspace(int m, int n, int variant, int nb, int nb_inner, size_t* bytes) {
   if (m < 0) return -1;
   if (n < 0) return -2;
-  if (variant < MLU_RL || variant > MLU_LA) return -3;
+  if (!valid_variant(variant)) return -3;
   if (nb < 1) return -4;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -5;
   if (!bytes) return -6;
@@ -484,7 +487,7 @@ int getrf_entry(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv
   if (lda < (n > 1 ? n : 1)) return -5;
   if (mn > 0 && !d_ipiv) return -6;
   if (!d_info) return -7;
-  if (variant < MLU_RL || variant > MLU_LA) return -8;
+  if (!valid_variant(variant)) return -8;
   if (nb < 1) return -9;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
   if (inner != MLU_RL && inner != MLU_LL) return -11;
@@ -530,10 +533,11 @@ int getrf_run(void* stream, int m, int n, double* dA, int lda, int32_t* d_ipiv, 
   Ctx c{dA, lda, m, n, d_ipiv, d_info, 0, &ws->panel, &ws->queue,
         precision == MLU_PREC_FP32 ? kPrecF32 : (precision == MLU_PREC_BF16 ? kPrecBF16 : kPrecF64), &epoch, inner};
   c.bi = nb_inner > 0 ? nb_inner : (nb < kPanelRegCols ? nb : kPanelRegCols);
+  c.sharing = variant != MLU_LA_NOWS;
 
   hipError_t e;
   if (variant == MLU_RL) e = run_rl(s, c, sched, iters_limit);
-  else if (variant == MLU_LA) e = run_la(s, c, sched, iters_limit);
+  else if (variant == MLU_LA || variant == MLU_LA_NOWS) e = run_la(s, c, sched, iters_limit);
   else e = run_ll(s, c, sched, iters_limit);
   return e == hipSuccess ? 0 : MLU_ERR_HIP;
 }
@@ -560,7 +564,7 @@ int mlu_dgetrf_noalloc(void* stream, int m, int n, double* dA, int lda, int32_t*
   if (lda < (n > 1 ? n : 1)) return -5;
   if (mn > 0 && !d_ipiv) return -6;
   if (!d_info) return -7;
-  if (variant < MLU_RL || variant > MLU_LA) return -8;
+  if (!valid_variant(variant)) return -8;
   if (nb < 1) return -9;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -10;
   if (inner != MLU_RL && inner != MLU_LL) return -11;

@@ -487,7 +487,7 @@ int mlu_dsgesv_ir(void* stream, int n, int nrhs, const double* dA, int lda, cons
   if (precision != MLU_PREC_FP64 && precision != MLU_PREC_FP32 && precision != MLU_PREC_BF16) return -10;
   if (!(tol >= 0.0)) return -11;
   if (max_iter < 0) return -12;
-  if (variant < MLU_RL || variant > MLU_LA) return -13;
+  if (!valid_variant(variant)) return -13;
   if (nb < 1) return -14;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -15;
   if (n > 0 && !d_ipiv) return -16;
@@ -593,7 +593,7 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   if (max_outer < 0) return -10;
   if (max_krylov < 1 || max_krylov > MLU_GMRES_MAX_KRYLOV) return -11;
   if (!(gmres_tol >= 0.0)) return -12;
-  if (variant < MLU_RL || variant > MLU_LA) return -13;
+  if (!valid_variant(variant)) return -13;
   if (nb < 1) return -14;
   if (nb_inner < 0 || nb_inner > MLU_MAX_NB_INNER) return -15;
   if (n > 0 && !d_ipiv) return -16;

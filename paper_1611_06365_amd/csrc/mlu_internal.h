@@ -1,10 +1,14 @@
 // Internal declarations shared by the HIP sources of libmlu (not part of the ABI).
 #pragma once
+#include "../../include/mlu.h"
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
 
 namespace mlu {
+
+// mlu_dgetrf's variant argument: one of the enum's values
+inline bool valid_variant(int v) { return v == MLU_RL || v == MLU_LL || v == MLU_LA || v == MLU_LA_NOWS; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 // Two consecutive doubles read from global memory with one 16-byte load at

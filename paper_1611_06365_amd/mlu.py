@@ -13,8 +13,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlu.so")
 
-MLU_RL, MLU_LL, MLU_LA = 0, 1, 2
-VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA}
+MLU_RL, MLU_LL, MLU_LA, MLU_LA_NOWS = 0, 1, 2, 4
+VARIANT_IDS = {"rl": MLU_RL, "ll": MLU_LL, "la": MLU_LA, "la_nows": MLU_LA_NOWS}
 MLU_ERR_HIP = -1000
 MLU_ERR_NOINIT = -1001
 MLU_INFO_SYNC_TIMEOUT = -999

@@ -61,7 +61,8 @@ def _getrf(**kw):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(m=-1), -2), (dict(n=-3), -3), (dict(dA=None), -4), (dict(lda=7), -5), (dict(d_ipiv=None), -6),
-    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(nb=0), -9), (dict(nb_inner=33), -10),
+    (dict(d_info=None), -7), (dict(variant=3), -8), (dict(variant=5), -8), (dict(variant=-1), -8),
+    (dict(variant=4, nb=0), -9), (dict(nb=0), -9), (dict(nb_inner=33), -10),
     (dict(nb_inner=-1), -10), (dict(inner=2), -11), (dict(inner=-1), -11), (dict(iters_limit=-2), -14),
     (dict(d_work=None), -15), (dict(work_bytes=16), -16),
 ])

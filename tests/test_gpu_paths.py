@@ -15,6 +15,7 @@
   * look-ahead with early termination at n = 16384 for every stop mode:
     normwise residual <= 1e-13, |L| <= 1, legal interchanges, realized widths
     that cover the matrix;
+  * look-ahead without worker sharing bit-identical to look-ahead;
   * one look-ahead call captured in a stream graph (its library stream forked
     and joined with events), replayed several times with other work and
     synchronizations between the replays: every replay bit-equal to the eager
@@ -228,6 +229,23 @@ def test_la_orders_off_the_tile_grid(n, recipe):
     print(f"la n={n} {recipe}: residual {res:.2e}, max|L| {lmax:.3f}", flush=True)
     assert res <= (1e-13 if recipe == "spd" else 1e-12) and lmax <= 1.0
     del F, A
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ worker sharing on and off
+@pytest.mark.parametrize("n,nb,recipe", [(3001, 64, "uniform"), (16384, 256, "spd")])
+def test_la_without_worker_sharing_is_bitwise_la(n, nb, recipe):
+    """MLU_LA_NOWS (the panel's workgroups do not join RU2 after PF3) does the
+    same arithmetic as MLU_LA: every tile is computed the same way whichever
+    workgroup takes it, so the factors and pivots are bit-identical."""
+    A = D.spd_bbt(n, seed=4, device=DEV) if recipe == "spd" else D.uniform01(n, seed=4, device=DEV)
+    F1, F2 = A.clone(), A.clone()
+    ip1, in1 = mlu.getrf(F1, variant="la", nb=nb, nb_inner=16)
+    ip2, in2 = mlu.getrf(F2, variant="la_nows", nb=nb, nb_inner=16)
+    torch.cuda.synchronize()
+    assert int(in1.item()) == 0 and int(in2.item()) == 0
+    assert torch.equal(ip1, ip2) and torch.equal(F1, F2)
+    del F1, F2, A
     torch.cuda.empty_cache()
 
 
