@@ -24,6 +24,13 @@ come from them:
                                      the next one, and the busy time and
                                      kernels of the other streams in between;
                                      with --iter, that iteration's kernels
+  grid --calib <dir> --config LABEL:RUN_A:RUN_B:RUN_C ... --kernel REGEX ... --copy-bytes N
+                                     per configuration and kernel: duration,
+                                     matrix-core busy fraction, calibrated HBM
+                                     bytes and their rate (run A: the MFMA
+                                     counters of the calibration run and a
+                                     kernel trace; run B: FETCH_SIZE; run C:
+                                     WRITE_SIZE)
   mfma --calib <dir> --run <dir> --kernel REGEX [--kernel REGEX ...] [--source F]
                                      matrix-core utilization of the matching
                                      kernels: SQ_VALU_MFMA_BUSY_CYCLES per
@@ -206,6 +213,54 @@ def mfma(calib_dir, run_dir, kernels, calib_kernel="k_mfma_peak"):
     return out
 
 
+def _durations(d: str):
+    """{dispatch_id: duration in ns} from the kernel trace of a run."""
+    out = {}
+    with open(_find(d, "kernel_trace.csv")) as f:
+        for r in csv.DictReader(f):
+            did = int(_col(r, "Dispatch_Id", "Dispatch-Id"))
+            out[did] = int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))
+    return out
+
+
+def grid(calib_dir, configs, kernels, copy_bytes, copy_kernel, calib_kernel="k_mfma_peak"):
+    """Per configuration and kernel: dispatches, average duration, matrix-core
+    busy fraction (normalized as in `mfma`, run A collecting the same counters
+    as the calibration run), calibrated HBM bytes per dispatch (FETCH_SIZE
+    from run B, WRITE_SIZE from run C, each scaled by the copy calibration of
+    its own run) and the rate those bytes make over the duration.  `configs`:
+    (label, run A with the MFMA counters and a kernel trace, run B, run C)."""
+    n_c, cal = counters(calib_dir, calib_kernel)
+    if n_c == 0:
+        raise RuntimeError(f"no {calib_kernel} dispatch in {calib_dir}")
+    cal_rate = cal["SQ_VALU_MFMA_BUSY_CYCLES"] / cal["GRBM_GUI_ACTIVE"]
+    rows = []
+    for label, da, db, dc in configs:
+        disp_a, disp_b, disp_c, dur = per_dispatch(da), per_dispatch(db), per_dispatch(dc), _durations(da)
+        fscale = copy_bytes / (_copy_dispatch(disp_b, "FETCH_SIZE", copy_kernel)[1] * 1024.0)
+        wscale = copy_bytes / (_copy_dispatch(disp_c, "WRITE_SIZE", copy_kernel)[1] * 1024.0)
+        for k in kernels:
+            ids = [i for i, (name, v) in disp_a.items() if re.search(k, name) and v.get("GRBM_GUI_ACTIVE")]
+            fv = [v["FETCH_SIZE"] for name, v in disp_b.values() if re.search(k, name) and "FETCH_SIZE" in v]
+            wv = [v["WRITE_SIZE"] for name, v in disp_c.values() if re.search(k, name) and "WRITE_SIZE" in v]
+            if not ids or not fv or not wv:
+                continue
+            # time-weighted: busy cycles over active cycles summed over the
+            # dispatches (a dispatch that finds no work weighs nothing)
+            busy = sum(disp_a[i][1]["SQ_VALU_MFMA_BUSY_CYCLES"] for i in ids) / \
+                sum(disp_a[i][1]["GRBM_GUI_ACTIVE"] for i in ids) / cal_rate
+            flops = 512.0 * sum(disp_a[i][1].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for i in ids) / len(ids)
+            fetch = sum(fv) / len(fv) * 1024.0 * fscale
+            write = sum(wv) / len(wv) * 1024.0 * wscale
+            ns = [dur[i] for i in ids if i in dur]
+            t = sum(ns) / len(ns) if ns else float("nan")
+            rows.append({"config": label, "kernel": k, "dispatches": len(ids), "avg_us": round(t / 1e3, 2),
+                         "mfma_busy_frac": round(busy, 4), "f64_gflop": round(flops / 1e9, 4),
+                         "fetch_bytes": round(fetch), "write_bytes": round(write),
+                         "hbm_gbs": round((fetch + write) / t, 1) if ns else None})
+    return rows
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -237,6 +292,12 @@ def main(argv=None) -> int:
     mm.add_argument("--run", required=True)
     mm.add_argument("--kernel", action="append", required=True)
     mm.add_argument("--source", default=None, help="kernel source whose sha1 the record carries")
+    g = sub.add_parser("grid")
+    g.add_argument("--calib", required=True)
+    g.add_argument("--config", action="append", required=True, metavar="LABEL:RUN_A:RUN_B:RUN_C")
+    g.add_argument("--kernel", action="append", required=True)
+    g.add_argument("--copy-bytes", type=int, required=True)
+    g.add_argument("--copy-kernel", default=r"AUnaryFunctor<double, double, double, .*MulFunctor")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(f"{'kernel':72s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
@@ -249,6 +310,16 @@ def main(argv=None) -> int:
         print("TRAFFIC_JSON: " + json.dumps(rec))
     elif a.cmd == "timeline":
         timeline(a.dir, a.main, a.per_factorization, a.min_grid, a.iter)
+    elif a.cmd == "grid":
+        cfgs = [tuple(c.split(":")) for c in a.config]
+        rows = grid(a.calib, cfgs, a.kernel, a.copy_bytes, a.copy_kernel)
+        print("| config | kernel | dispatches | avg us | MFMA busy | GFLOP (counted) | MB read | MB written | GB/s |")
+        print("|---|---|---|---|---|---|---|---|---|")
+        for r in rows:
+            print(f"| {r['config']} | {r['kernel']} | {r['dispatches']} | {r['avg_us']} | "
+                  f"{100 * r['mfma_busy_frac']:.1f}% | {r['f64_gflop']} | {r['fetch_bytes'] / 1e6:.1f} | "
+                  f"{r['write_bytes'] / 1e6:.1f} | {r['hbm_gbs']} |")
+        print("GRID_JSON: " + json.dumps(rows))
     elif a.cmd == "mfma":
         rec = mfma(a.calib, a.run, a.kernel)
         if a.source:
