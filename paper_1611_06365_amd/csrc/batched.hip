@@ -30,12 +30,14 @@
 
 #include <climits>
 #include <mutex>
+#include <type_traits>
 
 namespace mlu {
 namespace {
 
-constexpr int kBT = 512;           // threads per workgroup: one panel row each
-constexpr int kUC = 64;            // A12 columns staged per chunk
+// A12 columns staged per chunk: eight threads per column in the solve for U12
+template <int BT>
+constexpr int chunk_cols() { return BT / 8; }
 constexpr int kMaxN = MLU_BATCH_MAX_N;
 constexpr int kBatchDefaultNB = 16;   // panel width when the caller passes 0
 
@@ -48,16 +50,23 @@ constexpr bool panel_in_lds() {
   return !(sizeof(T) == 8 && NB == 32);
 }
 
-template <typename T, int NB>
+// Size classes: a workgroup of BT threads (one panel row each) factors
+// matrices of order at most BT; the batch is split into orders above 256,
+// above 128, and the rest, each class a persistent launch of its own.
+constexpr int kClasses = 3;
+constexpr int class_threads(int cls) { return cls == 0 ? 512 : (cls == 1 ? 256 : 128); }
+
+template <typename T, int NB, int BT>
 struct BatchLds {
   static constexpr bool kPL = panel_in_lds<T, NB>();
   static constexpr int kP = NB + 1;   // LDS pitch of the panel
-  T P[kPL ? kMaxN * kP : NB * kP];    // the factored panel (L11\U11 over L21), or its diagonal block only
+  T P[kPL ? BT * kP : NB * kP];       // the factored panel (L11\U11 over L21), or its diagonal block only
+  static constexpr int kUC = chunk_cols<BT>();
   T U[NB * kUC];           // U12 chunk
-  T cand[2][kBT / kWave][NB];   // each wave's candidate pivot row, by column parity
-  T wv[2][kBT / kWave];
-  int wr[2][kBT / kWave];
-  int16_t src[kMaxN];      // after the panel: the row now at position r came from src[r]
+  T cand[2][BT / kWave][NB];   // each wave's candidate pivot row, by column parity
+  T wv[2][BT / kWave];
+  int wr[2][BT / kWave];
+  int16_t src[BT];         // after the panel: the row now at position r came from src[r]
   int piv[NB];
   int item;
 };
@@ -142,13 +151,14 @@ __device__ __forceinline__ void wave_argmax_t(T& v, int& r) {
   r = rr;
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int BT>
 __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, int32_t* __restrict__ ipiv,
-                                           int32_t* __restrict__ info, BatchLds<T, NB>& L) {
-  constexpr int kP = BatchLds<T, NB>::kP;
-  constexpr bool kPL = BatchLds<T, NB>::kPL;
-  static_assert(kMaxN == kBT, "one panel row per thread");
-  constexpr int kTG = kBT / kUC;     // threads per column in the solve for U12
+                                           int32_t* __restrict__ info, BatchLds<T, NB, BT>& L) {
+  constexpr int kP = BatchLds<T, NB, BT>::kP;
+  constexpr bool kPL = BatchLds<T, NB, BT>::kPL;
+  constexpr int kUC = BatchLds<T, NB, BT>::kUC;
+  constexpr int kTG = BT / kUC;      // threads per column in the solve for U12 (n <= BT: one row per thread)
+  static_assert(kTG >= 1 && NB % kTG == 0 && kWave % kTG == 0, "solve layout");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // scalar: LDS slots of the wave
   int zero_col = INT_MAX;
@@ -184,7 +194,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
           T pm = L.wv[par][0];
           int p = L.wr[par][0];
 #pragma unroll
-          for (int w = 1; w < kBT / kWave; ++w)
+          for (int w = 1; w < BT / kWave; ++w)
             if (L.wv[par][w] > pm || (L.wv[par][w] == pm && L.wr[par][w] < p)) {
               pm = L.wv[par][w];
               p = L.wr[par][w];
@@ -222,7 +232,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         T pm = L.wv[par][0];
         int p = L.wr[par][0], ws = 0;
 #pragma unroll
-        for (int w = 1; w < kBT / kWave; ++w)
+        for (int w = 1; w < BT / kWave; ++w)
           if (L.wv[par][w] > pm || (L.wv[par][w] == pm && L.wr[par][w] < p)) {
             pm = L.wv[par][w];
             p = L.wr[par][w];
@@ -287,7 +297,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     for (int c = 0; c < nb; ++c) any |= L.piv[c] != c;
     if (any) {
       const int ncol = n - nb;
-      for (int idx = tid; idx < 2 * ncol; idx += kBT) {   // a lane pair is in range together
+      for (int idx = tid; idx < 2 * ncol; idx += BT) {   // a lane pair is in range together
         const int col = idx >> 1, h = idx & 1;
         const int g = col < j ? col : col + nb;
         int tg[NB];
@@ -335,7 +345,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         // its 16 x 16 blocks, with the next block's C loads issued before the
         // current one's products
         typedef typename Mfma<T>::acc_t acc_t;
-        constexpr int kWaves = kBT / kWave;
+        constexpr int kWaves = BT / kWave;
         const int li = lane & 15, lq = lane >> 4;
         const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16, npair = nrb * nsb;
         T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
@@ -380,7 +390,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         // of the chunk's 16-column blocks, and every C load of the band is
         // issued before the first product
         typedef typename Mfma<T>::acc_t acc_t;
-        constexpr int kWaves = kBT / kWave, kSB = kUC / 16;
+        constexpr int kWaves = BT / kWave, kSB = kUC / 16;
         const int li = lane & 15, lq = lane >> 4;
         const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16;
         T* const C = A + (size_t)(j + nb) * lda + j + nb + c0;
@@ -423,13 +433,16 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
 }
 
 // order[] := matrix indices by decreasing order n (counting sort, one
-// workgroup); entries with an invalid order are placed last.
+// workgroup); entries with an invalid order are placed last.  bounds[c] ..
+// bounds[c + 1] is the range of size class c (orders above 256, above 128,
+// the rest and the invalid ones); the classes' queue counters are cleared.
 __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int32_t* __restrict__ d_n, int max_n,
-                                                      int32_t* __restrict__ order, unsigned* __restrict__ queue) {
+                                                      int32_t* __restrict__ order, unsigned* __restrict__ queue,
+                                                      int32_t* __restrict__ bounds) {
   __shared__ int cnt[kMaxN + 2];
   const int tid = threadIdx.x;
   for (int b = tid; b < kMaxN + 2; b += blockDim.x) cnt[b] = 0;
-  if (tid == 0) *queue = 0u;
+  if (tid < kClasses) queue[tid] = 0u;
   __syncthreads();
   auto bucket = [&](int i) {
     const int n = d_n[i];
@@ -444,32 +457,40 @@ __global__ __launch_bounds__(1024) void k_batch_order(int batch, const int32_t* 
       cnt[b] = s;
       s += c;
     }
+    // class c holds the orders above class_threads(c + 1): buckets below kMaxN - that
+    bounds[0] = 0;
+    for (int c = 1; c < kClasses; ++c) bounds[c] = cnt[kMaxN - class_threads(c)];
+    bounds[kClasses] = batch;
   }
   __syncthreads();
   for (int i = tid; i < batch; i += blockDim.x) order[atomicAdd(&cnt[bucket(i)], 1)] = i;
 }
 
-// Waves per SIMD each instantiation is built for, i.e. resident workgroups
-// per CU x 8 waves / 4 SIMDs: two workgroups per CU, three for FP32 with
-// 16-column panels (so that one matrix's panel, a latency chain, runs beside
-// another's work).  Registers are held to it (the second launch bound is the
-// minimum waves per execution unit).
+// Waves per SIMD each instantiation is built for: 4 (two 512-thread
+// workgroups per CU, four of 256, eight of 128), 6 for FP32 with 16-column
+// panels, so that one matrix's panel, a latency chain, runs beside another's
+// work.  Registers are held to it (the second launch bound is the minimum
+// waves per execution unit).
 template <typename T, int NB>
-constexpr int batched_min_blocks() {
-  return (sizeof(T) == 4 && NB == 16 ? 3 : 2) * (kBT / kWave) / 4;
+constexpr int batched_min_waves() {
+  return sizeof(T) == 4 && NB == 16 ? 6 : 4;
 }
 
-template <typename T, int NB>
-__global__ __launch_bounds__(kBT, (batched_min_blocks<T, NB>())) void k_getrf_batched(int batch, const int32_t* __restrict__ d_n, T* const* d_A,
-                                                       const int32_t* __restrict__ d_lda, int32_t* const* d_ipiv,
-                                                       int32_t* __restrict__ d_info, int max_n,
-                                                       const int32_t* __restrict__ order, unsigned* queue) {
+// Persistent: workgroups take the matrices of size class `cls` (the range
+// bounds[cls] .. bounds[cls + 1] of order[]) from that class's queue.
+template <typename T, int NB, int BT>
+__global__ __launch_bounds__(BT, (batched_min_waves<T, NB>())) void k_getrf_batched(
+    int cls, const int32_t* __restrict__ d_n, T* const* d_A, const int32_t* __restrict__ d_lda,
+    int32_t* const* d_ipiv, int32_t* __restrict__ d_info, int max_n, const int32_t* __restrict__ order,
+    unsigned* queue, const int32_t* __restrict__ bounds) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  BatchLds<T, NB>& L = *reinterpret_cast<BatchLds<T, NB>*>(smem);
+  BatchLds<T, NB, BT>& L = *reinterpret_cast<BatchLds<T, NB, BT>*>(smem);
+  const int lo = __builtin_amdgcn_readfirstlane(bounds[cls]);
+  const int hi = __builtin_amdgcn_readfirstlane(bounds[cls + 1]);
   while (true) {
     if (threadIdx.x == 0) {
-      const unsigned t = atomicAdd(queue, 1u);
-      L.item = t < (unsigned)batch ? order[t] : -1;
+      const unsigned t = atomicAdd(&queue[cls], 1u);
+      L.item = t < (unsigned)(hi - lo) ? order[lo + (int)t] : -1;
     }
     __syncthreads();
     // the item and the matrix's order are the same in every thread: make them
@@ -480,38 +501,51 @@ __global__ __launch_bounds__(kBT, (batched_min_blocks<T, NB>())) void k_getrf_ba
     if (i < 0) break;
     const int n = __builtin_amdgcn_readfirstlane(d_n[i]);
     const int lda = __builtin_amdgcn_readfirstlane(d_lda[i]);
-    const bool bad = n < 0 || n > max_n || lda < (n > 1 ? n : 1);
+    // (an order above BT cannot be in this class: the sort put it in a larger one)
+    const bool bad = n < 0 || n > max_n || n > BT || lda < (n > 1 ? n : 1);
     if (bad || n == 0) {
       if (threadIdx.x == 0) d_info[i] = bad ? -1 : 0;
     } else {
-      factor_one<T, NB>(n, d_A[i], lda, d_ipiv[i], &d_info[i], L);
+      factor_one<T, NB, BT>(n, d_A[i], lda, d_ipiv[i], &d_info[i], L);
     }
     __syncthreads();
   }
 }
 
-// Workgroups of k_getrf_batched<T, NB> resident per CU (registers and LDS),
-// found once by batched_set_lds_limits.
-int g_resident[2][2] = {{1, 1}, {1, 1}};
+// Workgroups of k_getrf_batched<T, NB, class_threads(c)> resident per CU
+// (registers and LDS), found once by batched_set_lds_limits.
+int g_resident[2][2][kClasses] = {};
 
-template <typename T, int NB>
-int batched_resident() {
-  return g_resident[sizeof(T) == 8 ? 0 : 1][NB == 16 ? 0 : 1];
-}
-
-template <typename T, int NB>
-hipError_t launch_nb(hipStream_t s, int batch, const int32_t* d_n, T* const* d_A, const int32_t* d_lda,
-                     int32_t* const* d_ipiv, int32_t* d_info, int max_n, const int32_t* order, unsigned* queue) {
+template <typename T, int NB, int C>
+hipError_t launch_class(hipStream_t s, int batch, const int32_t* d_n, T* const* d_A, const int32_t* d_lda,
+                        int32_t* const* d_ipiv, int32_t* d_info, int max_n, const int32_t* order, unsigned* queue,
+                        const int32_t* bounds) {
+  constexpr int BT = class_threads(C);
   int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = sizeof(BatchLds<T, NB>);
-  const int per_cu = batched_resident<T, NB>();
+  const int per_cu = g_resident[sizeof(T) == 8 ? 0 : 1][NB == 16 ? 0 : 1][C];
   const int grid = cus * per_cu < batch ? cus * per_cu : batch;
-  hipLaunchKernelGGL((k_getrf_batched<T, NB>), dim3(grid), dim3(kBT), lds, s, batch, d_n, d_A, d_lda, d_ipiv, d_info,
-                     max_n, order, queue);
+  hipLaunchKernelGGL((k_getrf_batched<T, NB, BT>), dim3(grid), dim3(BT), sizeof(BatchLds<T, NB, BT>), s, C, d_n,
+                     d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds);
   return hipGetLastError();
+}
+
+// One persistent launch per size class that can hold an order up to max_n
+// (the last class also takes the invalid entries), largest first.
+template <typename T, int NB>
+hipError_t launch_nb(hipStream_t s, int batch, const int32_t* d_n, T* const* d_A, const int32_t* d_lda,
+                     int32_t* const* d_ipiv, int32_t* d_info, int max_n, const int32_t* order, unsigned* queue,
+                     const int32_t* bounds) {
+  hipError_t e = hipSuccess;
+  if (max_n > class_threads(1))
+    e = launch_class<T, NB, 0>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds);
+  if (e == hipSuccess && max_n > class_threads(2))
+    e = launch_class<T, NB, 1>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds);
+  if (e == hipSuccess)
+    e = launch_class<T, NB, 2>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds);
+  return e;
 }
 
 template <typename T>
@@ -530,13 +564,17 @@ int launch_batched(void* stream, int batch, const int32_t* d_n, T* const* d_A, c
   if (batch == 0) return 0;
   if (batched_set_lds_limits() != hipSuccess) return MLU_ERR_HIP;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // workspace: the classes' queue counters (words 0..2), their bounds in
+  // order[] (words 16..19), then order[]
   unsigned* queue = reinterpret_cast<unsigned*>(d_work);
+  int32_t* bounds = reinterpret_cast<int32_t*>(d_work) + 16;
   int32_t* order = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_work) + 256);
-  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, batch, d_n, max_n, order, queue);
+  hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, batch, d_n, max_n, order, queue, bounds);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   const int use = nb != 0 ? nb : kBatchDefaultNB;
-  const hipError_t e = use == 16 ? launch_nb<T, 16>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue)
-                                 : launch_nb<T, 32>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue);
+  const hipError_t e =
+      use == 16 ? launch_nb<T, 16>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds)
+                : launch_nb<T, 32>(s, batch, d_n, d_A, d_lda, d_ipiv, d_info, max_n, order, queue, bounds);
   return e == hipSuccess ? 0 : MLU_ERR_HIP;
 }
 
@@ -553,16 +591,26 @@ hipError_t batched_set_lds_limits() {
   std::lock_guard<std::mutex> lk(mu);
   if (done) return hipSuccess;
   hipError_t e = hipSuccess;
-  auto set = [&](const void* fn, size_t bytes, int& resident) {
+  auto set = [&](const void* fn, size_t bytes, int threads, int& resident) {
     if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     int blocks = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kBT, bytes);
-    if (e == hipSuccess) resident = blocks < 1 ? 1 : (blocks > 4 ? 4 : blocks);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, threads, bytes);
+    if (e == hipSuccess) resident = blocks < 1 ? 1 : (blocks > 16 ? 16 : blocks);
   };
-  set(reinterpret_cast<const void*>(&k_getrf_batched<double, 16>), sizeof(BatchLds<double, 16>), g_resident[0][0]);
-  set(reinterpret_cast<const void*>(&k_getrf_batched<double, 32>), sizeof(BatchLds<double, 32>), g_resident[0][1]);
-  set(reinterpret_cast<const void*>(&k_getrf_batched<float, 16>), sizeof(BatchLds<float, 16>), g_resident[1][0]);
-  set(reinterpret_cast<const void*>(&k_getrf_batched<float, 32>), sizeof(BatchLds<float, 32>), g_resident[1][1]);
+  auto set_all = [&](auto tag, auto nbc, int ti, int ni) {
+    typedef decltype(tag) T;
+    constexpr int NB = decltype(nbc)::value;
+    set(reinterpret_cast<const void*>(&k_getrf_batched<T, NB, 512>), sizeof(BatchLds<T, NB, 512>), 512,
+        g_resident[ti][ni][0]);
+    set(reinterpret_cast<const void*>(&k_getrf_batched<T, NB, 256>), sizeof(BatchLds<T, NB, 256>), 256,
+        g_resident[ti][ni][1]);
+    set(reinterpret_cast<const void*>(&k_getrf_batched<T, NB, 128>), sizeof(BatchLds<T, NB, 128>), 128,
+        g_resident[ti][ni][2]);
+  };
+  set_all(double(), std::integral_constant<int, 16>(), 0, 0);
+  set_all(double(), std::integral_constant<int, 32>(), 0, 1);
+  set_all(float(), std::integral_constant<int, 16>(), 1, 0);
+  set_all(float(), std::integral_constant<int, 32>(), 1, 1);
   if (e == hipSuccess) done = true;
   return e;
 }
