@@ -310,7 +310,9 @@ int mlu_dsgesv_gmres_ir(void *stream, int n, const double *dA, int lda, const do
  *           rounding), 0 for the default (16).
  *  d_work   mlu_getrf_batched_workspace(batch) bytes.
  * Matrices are processed largest first (a device counting sort), one per
- * 512-thread workgroup at a time from an atomic queue.  The call enqueues
+ * workgroup at a time from atomic queues, in three size classes (orders above
+ * 256, above 128, the rest: workgroups of 512, 256 and 128 threads, one
+ * persistent launch per class that max_n can reach).  The call enqueues
  * kernels only (no memset): it can be captured in a stream graph.
  * Returns 0, -i for an invalid argument i, or MLU_ERR_HIP.
  */

@@ -64,6 +64,28 @@ def test_batched_fp64_against_oracle(nb):
         assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-13, (i, n)
 
 
+@pytest.mark.parametrize("top,max_n", [(128, None), (200, None), (256, 512), (100, 200)])
+def test_batched_size_classes(top, max_n):
+    """Batches whose largest order (or stated max_n) leaves some of the three
+    size classes (orders above 256, above 128, the rest) empty or not
+    launched, orders at the class edges included, against the oracle."""
+    rng = np.random.default_rng(top)
+    ns = [n for n in (1, 64, 127, 128, 129, 200, 255, 256) if n <= top] + list(rng.integers(1, top + 1, 20))
+    mats = [G.uniform01(int(n), seed=500 + i) for i, n in enumerate(ns)]
+    dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
+    plan = mlu.BatchPlan(dmats, max_n=max_n, nb=32)
+    plan.run()
+    info = host(plan.info)
+    for i, (a, d) in enumerate(zip(mats, dmats)):
+        F = host(d)
+        piv = (host(plan.pivots(i)) - 1).tolist()
+        R = a.copy()
+        opiv, oinfo = O.getrf(R, "rl", nb=32)
+        assert info[i] == oinfo == 0, i
+        assert piv == opiv, (i, a.shape[0])
+        assert np.abs(F - R).max() <= 1e-12 * max(1.0, np.abs(R).max()), (i, a.shape[0])
+
+
 @pytest.mark.parametrize("nb", [0, 32])
 def test_batched_known_answer_and_zero_pivot(nb):
     mats, expect = [], []
