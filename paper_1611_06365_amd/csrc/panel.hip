@@ -3,8 +3,10 @@
 //
 // The m x bw block is held in registers by nwg cooperating workgroups
 // ("workers") of 512 threads.  Worker 0 (the leader) holds rows 0..511, one per
-// thread; worker w >= 1 holds rows 512 + (w-1)*1024 + t + 512*k (thread t,
-// k = 0, 1).  Rows 0..bw-1 (the diagonal rows) therefore always live in the
+// thread; worker w >= 1 holds KR rows per thread, rows 512 + (w-1)*512*KR + t +
+// 512*k (thread t, k < KR): one row per thread while that takes at most 32
+// workers (m <= 16384: as many CUs as the look-ahead leaves to the panel), two
+// beyond.  Rows 0..bw-1 (the diagonal rows) therefore always live in the
 // leader.
 //
 // Per column c (exact mode):
@@ -825,6 +827,19 @@ hipError_t launch_panel(hipStream_t s, double* A, int lda, int m, int bw, int ro
     hipLaunchKernelGGL((k_panel<BW, kPanelWideWG, 1>), dim3(nwg), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info,
                        work, nwg, epoch, cl, cr, ns, lb, skip);
   } else {
+    // one row per thread while that takes at most 32 workers (half the work
+    // per thread in every column step), two rows per thread beyond
+    const int nwg1 = m <= NT ? 1 : 1 + (m - NT + NT - 1) / NT;
+    if (nwg1 <= 16) {
+      hipLaunchKernelGGL((k_panel<BW, 16, 1>), dim3(nwg1), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv, info, work,
+                         nwg1, epoch, cl, cr, ns, lb, skip);
+      return hipGetLastError();
+    }
+    if (nwg1 <= 32) {
+      hipLaunchKernelGGL((k_panel<BW, kPanelMaxWG, 1>), dim3(nwg1), dim3(NT), 0, s, A, lda, m, bw, row0, ipiv,
+                         info, work, nwg1, epoch, cl, cr, ns, lb, skip);
+      return hipGetLastError();
+    }
     const int nwg = m <= NT ? 1 : 1 + (m - NT + 2 * NT - 1) / (2 * NT);
     if (nwg > kPanelMaxWG) return hipErrorInvalidValue;
     if (nwg <= 16)
