@@ -8,11 +8,13 @@
 // 512-thread workgroups takes matrices from an atomic queue in that order.
 // One workgroup factors one matrix at a time, NB (16 or 32) columns per step:
 //   1. the (n - j) x NB panel is held in registers, one row per thread, and
-//      factored with partial pivoting.  Rows are not moved: each thread
-//      tracks the position its row has reached under the interchanges.  Per
-//      column, a DPP wave argmax (first position on ties), each wave's best
-//      row copied into LDS, one barrier, then every thread picks the winner,
-//      reads its row from LDS and updates its own row in registers;
+//      factored with partial pivoting.  Diagonal pivots are tried first (a
+//      pass with two barriers in all, checked as it goes, kept when every
+//      check holds); otherwise, per column: rows are not moved, each thread
+//      tracks the position its row has reached under the interchanges, a DPP
+//      wave argmax (first position on ties), each wave's best row copied into
+//      LDS, one barrier, then every thread picks the winner, reads its row
+//      from LDS and updates its own row in registers;
 //   2. the panel's interchanges are applied to the columns outside it,
 //      gathered: a lane pair owns a column and loads every moved row before
 //      storing any (no chain of dependent swaps);
@@ -162,6 +164,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // scalar: LDS slots of the wave
   int zero_col = INT_MAX;
+  bool spec = true;   // diagonal pivots tried first, until a panel of this matrix refutes them
   for (int j = 0; j < n; j += NB) {
     const int nb = min(NB, n - j), rows = n - j;
     // 1. the panel in registers, one row per thread.  Rows are not moved
@@ -170,15 +173,84 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     //    still below the diagonal (live); the search breaks ties by position.
     const int r = tid;
     T v[NB];
-    {
+    auto load_panel = [&]() {
       const bool own = r < rows;
       const T* a = A + (size_t)(j + (own ? r : 0)) * lda + j;
 #pragma unroll
       for (int cc = 0; cc < NB; ++cc) v[cc] = (own && cc < nb) ? a[cc] : T(0);
-    }
+    };
+    load_panel();
     int pos = r;
     bool live = r < rows;
-    if (wave * kWave >= rows) {
+    // Speculative pass: the pivot of every column is taken to be the diagonal
+    // row, which is the partial pivoting choice exactly when no row below it
+    // holds a larger |a(r, c)| at its column step (a tie keeps the diagonal
+    // row, as the first-position rule does) and the pivot is not a NaN.  Wave
+    // 0, whose lanes hold rows 0..63 and so every pivot row, eliminates its
+    // rows alone, each entry of the pivot row read from lane c as it is used
+    // (the updates are selected, not branched, so every lane reads it); it
+    // then writes the pivot rows into LDS, and the other waves eliminate
+    // theirs against them with no barrier per column.  Every row goes through
+    // the same operations, in the same order, as in the column steps below,
+    // so a pass whose checks all hold leaves what they would leave; otherwise
+    // the panel, still untouched in memory, is loaded again and factored by
+    // the column steps, and the rest of the matrix goes without speculation.
+    bool done = false;
+    if (spec) {
+      bool fail = false;
+      if (wave == 0) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c < nb) {
+            const T pv = lane_val(v[c], c);
+            const bool below = r > c && r < rows;
+            if (pv != pv || (below && fabs(v[c]) > fabs(pv))) fail = true;
+            const bool upd = below && pv != T(0);
+            const T l = upd ? v[c] / pv : T(0);
+            v[c] = upd ? l : v[c];
+#pragma unroll
+            for (int cc = c + 1; cc < NB; ++cc) {
+              const T x = lane_val(v[cc], c);   // lane c's row is not updated at its own column
+              const T y = v[cc] - l * x;
+              v[cc] = upd ? y : v[cc];
+            }
+          }
+        }
+        if (r < nb) {
+#pragma unroll
+          for (int cc = 0; cc < NB; ++cc) L.P[r * kP + cc] = v[cc];
+        }
+      }
+      __syncthreads();
+      if (wave > 0 && r < rows) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c < nb) {
+            const T* prow = &L.P[c * kP];
+            const T pv = prow[c];
+            if (fabs(v[c]) > fabs(pv)) fail = true;
+            if (pv != T(0)) {
+              const T l = v[c] / pv;
+              v[c] = l;
+#pragma unroll
+              for (int cc = c + 1; cc < NB; ++cc) v[cc] -= l * prow[cc];
+            }
+          }
+        }
+      }
+      done = __syncthreads_or(fail ? 1 : 0) == 0;
+      if (done) {
+        for (int c = 0; c < nb; ++c)
+          if (L.P[c * kP + c] == T(0) && j + c < zero_col) zero_col = j + c;
+        if (tid < nb) L.piv[tid] = tid;
+      } else {
+        spec = false;
+        load_panel();
+      }
+    }
+    if (done) {
+      // the rows keep their positions
+    } else if (wave * kWave >= rows) {
       // a wave with no row of the panel takes part in the column steps'
       // barriers only (the same count: the second one comes with a column of
       // NaNs, known to every thread from LDS)

@@ -64,6 +64,43 @@ def test_batched_fp64_against_oracle(nb):
         assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-13, (i, n)
 
 
+def _planted(n, seed, row, col, value=1.0e6):
+    """A = B B^T + n I (diagonal pivots throughout) with one entry planted
+    below the diagonal, which makes row `row` the pivot of column `col`."""
+    a = G.spd_bbt(n, seed=seed)
+    a[row, col] = value
+    return a
+
+
+@pytest.mark.parametrize("nb", [16, 32])
+def test_batched_diagonal_speculation_and_its_misses(nb):
+    """Diagonal pivots are tried first on every panel: matrices whose pivots
+    stay on the diagonal, and matrices where the guess fails in the first
+    panel (in the wave holding the pivot rows or in another one) or only in a
+    later panel (the rest of the matrix then goes column by column), all
+    against the oracle."""
+    mats = [G.spd_bbt(n, seed=300 + n) for n in (5, 40, 100, 300, 500)]
+    mats += [_planted(100, 1, 10, 3), _planted(500, 2, 400, 5), _planted(300, 3, 150, 40),
+             _planted(500, 4, 480, 100), _planted(200, 5, 199, 198)]
+    dmats = [torch.from_numpy(a.copy()).to(DEV) for a in mats]
+    plan = mlu.getrf_batched(dmats, nb=nb)
+    info = host(plan.info)
+    for i, (a, d) in enumerate(zip(mats, dmats)):
+        n = a.shape[0]
+        F = host(d)
+        piv = (host(plan.pivots(i)) - 1).tolist()
+        R = a.copy()
+        opiv, oinfo = O.getrf(R, "rl", nb=32)
+        assert info[i] == oinfo == 0, i
+        assert piv == opiv, (i, n)
+        assert np.abs(F - R).max() <= 1e-12 * max(1.0, np.abs(R).max()), (i, n)
+        assert I.postcondition(a, F, piv)["rel_frob"] <= 1e-13, (i, n)
+    # the planted rows are the pivots of their columns, the others stay put
+    assert (host(plan.pivots(5)) - 1)[3] == 10
+    assert (host(plan.pivots(7)) - 1)[40] == 150
+    assert all((host(plan.pivots(k)) - 1).tolist() == list(range(mats[k].shape[0])) for k in range(5))
+
+
 @pytest.mark.parametrize("top,max_n", [(128, None), (200, None), (256, 512), (100, 200)])
 def test_batched_size_classes(top, max_n):
     """Batches whose largest order (or stated max_n) leaves some of the three
