@@ -23,7 +23,9 @@
 //      matrix cores (v_mfma 16 x 16 x 4 in the operand precision), 16 x 16
 //      blocks spread over the waves, A21 read from an LDS copy of the panel
 //      or, in FP64 with 32-column panels (two workgroups per CU instead of
-//      one), from global memory right after the panel was stored there.
+//      one), from global memory right after the panel was stored there.  That
+//      form blocks on two levels: panels go in pairs, and the columns beyond
+//      a pair take both panels' updates in one pass.
 // Waves that hold no row of the current panel only take part in its
 // barriers.
 // Matrices are row-major (element (i, j) at A[i*lda + j]), in place.
@@ -64,7 +66,7 @@ struct BatchLds {
   static constexpr int kP = NB + 1;   // LDS pitch of the panel
   T P[kPL ? BT * kP : NB * kP];       // the factored panel (L11\U11 over L21), or its diagonal block only
   static constexpr int kUC = chunk_cols<BT>();
-  T U[NB * kUC];           // U12 chunk
+  T U[kPL ? NB * kUC : 2 * NB * kUC];   // U12 chunk (two panels' in the two-level form)
   T cand[2][BT / kWave][NB];   // each wave's candidate pivot row, by column parity
   T wv[2][BT / kWave];
   int wr[2][BT / kWave];
@@ -165,6 +167,92 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // scalar: LDS slots of the wave
   int zero_col = INT_MAX;
   bool spec = true;   // diagonal pivots tried first, until a panel of this matrix refutes them
+  // Two-level blocking (the form whose A21 is read back from global
+  // memory): panels are taken in pairs A, B of NB columns.  After A, only
+  // B's columns get A's update; A's U12 rows of the columns beyond the pair
+  // are solved in place, and those columns wait.  After B, per chunk of the
+  // columns beyond: B's rows get A's update and are solved for B's U12 rows,
+  // then the rows below both panels take both rank-NB updates in one pass
+  // over their C entries (half the trailing traffic of one pass per
+  // panel).  B's interchanges reach the pending rows and A's L rows alike,
+  // so they commute with A's deferred update, and every entry receives the
+  // same products in the same order as with one pass per panel.
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int kWaves = BT / kWave, kSB = kUC / 16;
+  const int li = lane & 15, lq = lane >> 4;
+  // U12 := trilu(L11)^-1 A12 on rows jp..jp+NB-1 (the panel just factored,
+  // its diagonal block in P) of the columns [col0, col0 + cw), kTG threads
+  // per column; in place, and into U when it is given
+  auto solve_u12 = [&](int jp, int col0, int cw, T* U) {
+    const int c = tid / kTG, t = tid % kTG;
+    const bool ok = c < cw;
+    T* a = A + (size_t)jp * lda + col0 + c;
+    T x[NB / kTG];
+#pragma unroll
+    for (int i = 0; i < NB / kTG; ++i) x[i] = ok ? a[(size_t)(kTG * i + t) * lda] : T(0);
+#pragma unroll
+    for (int k = 0; k < NB - 1; ++k) {
+      const T xk = __shfl(x[k / kTG], (lane & ~(kTG - 1)) | (k % kTG));
+#pragma unroll
+      for (int i = k / kTG; i < NB / kTG; ++i)
+        if (kTG * i + t > k) x[i] -= L.P[(kTG * i + t) * kP + k] * xk;
+    }
+#pragma unroll
+    for (int i = 0; i < NB / kTG; ++i) {
+      if (U != nullptr) U[(kTG * i + t) * kUC + c] = x[i];
+      if (ok && kTG * i + t > 0) a[(size_t)(kTG * i + t) * lda] = x[i];
+    }
+  };
+  // rows [r0, r1) of the columns [col0, col0 + cw) minus A21_p U_p for the
+  // np panels p at columns jA (U in the first buffer) and jB (the second),
+  // on the matrix cores: wave w takes the 16-row bands w, w + 8, ...; per
+  // band and panel a lane loads its A21 fragments (from the panel stored
+  // just before, still in cache) once for all of the chunk's 16-column
+  // blocks, and every C load of the band is issued before the first product
+  auto c_update = [&](int r0, int r1, int col0, int cw, int np, int jA, int jB) {
+    const int R = r1 - r0;
+    const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16;
+    T* const C = A + (size_t)r0 * lda + col0;
+    for (int rb = wave; rb < nrb; rb += kWaves) {
+      const int arow = min(rb * 16 + li, R - 1);   // a clamped row is computed and not stored
+      acc_t acc[kSB];
+#pragma unroll
+      for (int sb = 0; sb < kSB; ++sb) {
+        const int col = min(sb * 16 + li, cw - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = min(rb * 16 + Mfma<T>::row_of(lq, r), R - 1);
+          acc[sb][r] = sb < nsb ? C[(size_t)row * lda + col] : T(0);
+        }
+      }
+      for (int p = 0; p < np; ++p) {
+        const T* const A21 = A + (size_t)r0 * lda + (p == 0 ? jA : jB);
+        const T* const U = L.U + p * NB * kUC;
+        T af[NB / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < NB / 4; ++s4) af[s4] = A21[(size_t)arow * lda + 4 * s4 + lq];
+#pragma unroll
+        for (int sb = 0; sb < kSB; ++sb) {
+          if (sb < nsb) {
+            const int col = min(sb * 16 + li, cw - 1);
+#pragma unroll
+            for (int s4 = 0; s4 < NB / 4; ++s4)
+              acc[sb] = Mfma<T>::run(af[s4], -U[(4 * s4 + lq) * kUC + col], acc[sb]);
+          }
+        }
+      }
+#pragma unroll
+      for (int sb = 0; sb < kSB; ++sb) {
+        if (sb < nsb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rb * 16 + Mfma<T>::row_of(lq, r);
+            if (sb * 16 + li < cw && row < R) C[(size_t)row * lda + sb * 16 + li] = acc[sb][r];
+          }
+        }
+      }
+    }
+  };
   for (int j = 0; j < n; j += NB) {
     const int nb = min(NB, n - j), rows = n - j;
     // 1. the panel in registers, one row per thread.  Rows are not moved
@@ -383,6 +471,40 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
       }
     }
     __syncthreads();   // P, and the interchanged columns, visible to the workgroup
+    if constexpr (!kPL) {
+      // 3, two-level: j is panel A or panel B of its pair
+      if (((j / NB) & 1) == 0) {
+        const int jb = j + nb, nbB = min(NB, n - jb), cS = jb + nbB;
+        // B's columns: A's U12 rows, then A's update of the rows below A
+        for (int c0 = jb; c0 < cS; c0 += kUC) {
+          const int cw = min(kUC, cS - c0);
+          solve_u12(j, c0, cw, L.U);
+          __syncthreads();
+          c_update(jb, n, c0, cw, 1, j, j);
+          __syncthreads();
+        }
+        // A's U12 rows of the columns beyond the pair, in place
+        for (int c0 = cS; c0 < n; c0 += kUC) solve_u12(j, c0, min(kUC, n - c0), nullptr);
+        __syncthreads();
+      } else {
+        const int ja = j - NB, cS = j + nb;
+        for (int c0 = cS; c0 < n; c0 += kUC) {
+          const int cw = min(kUC, n - c0);
+          for (int e = tid; e < NB * kUC; e += BT) {   // A's U12 rows of the chunk
+            const int k = e / kUC, c = e % kUC;
+            L.U[e] = c < cw ? A[(size_t)(ja + k) * lda + c0 + c] : T(0);
+          }
+          __syncthreads();
+          c_update(j, cS, c0, cw, 1, ja, ja);   // B's rows: A's update
+          __syncthreads();
+          solve_u12(j, c0, cw, L.U + NB * kUC);   // then B's U12 rows
+          __syncthreads();
+          c_update(cS, n, c0, cw, 2, ja, j);   // the rows below both: both updates
+          __syncthreads();
+        }
+      }
+      continue;
+    }
     // 3. per chunk of kUC right columns: U12 := trilu(A11)^-1 A12 (kTG
     //    threads per column, forward substitution), then A22 -= A21 U12 on
     //    the matrix cores, 16 x 16 blocks spread over the waves.  (Only a
