@@ -24,8 +24,8 @@
 //      blocks spread over the waves, A21 read from an LDS copy of the panel
 //      or, in FP64 with 32-column panels (two workgroups per CU instead of
 //      one), from global memory right after the panel was stored there.  That
-//      form blocks on two levels: panels go in pairs, and the columns beyond
-//      a pair take both panels' updates in one pass.
+//      form groups the panels in pairs: the columns beyond a pair take both
+//      panels' updates in one pass.
 // Waves that hold no row of the current panel only take part in its
 // barriers.
 // Matrices are row-major (element (i, j) at A[i*lda + j]), in place.
@@ -44,6 +44,7 @@ template <int BT>
 constexpr int chunk_cols() { return BT / 8; }
 constexpr int kMaxN = MLU_BATCH_MAX_N;
 constexpr int kBatchDefaultNB = 16;   // panel width when the caller passes 0
+constexpr int kGroup = 2;             // panels whose updates of the columns beyond them go in one pass
 
 // Whether the factored panel is kept in LDS for the trailing update (A21
 // read from there) or read back from global memory: LDS for every form but
@@ -66,7 +67,7 @@ struct BatchLds {
   static constexpr int kP = NB + 1;   // LDS pitch of the panel
   T P[kPL ? BT * kP : NB * kP];       // the factored panel (L11\U11 over L21), or its diagonal block only
   static constexpr int kUC = chunk_cols<BT>();
-  T U[kPL ? NB * kUC : 2 * NB * kUC];   // U12 chunk (two panels' in the two-level form)
+  T U[kPL ? NB * kUC : kGroup * NB * kUC];   // U12 chunk (one per panel of a group in the grouped form)
   T cand[2][BT / kWave][NB];   // each wave's candidate pivot row, by column parity
   T wv[2][BT / kWave];
   int wr[2][BT / kWave];
@@ -167,16 +168,17 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // scalar: LDS slots of the wave
   int zero_col = INT_MAX;
   bool spec = true;   // diagonal pivots tried first, until a panel of this matrix refutes them
-  // Two-level blocking (the form whose A21 is read back from global
-  // memory): panels are taken in pairs A, B of NB columns.  After A, only
-  // B's columns get A's update; A's U12 rows of the columns beyond the pair
-  // are solved in place, and those columns wait.  After B, per chunk of the
-  // columns beyond: B's rows get A's update and are solved for B's U12 rows,
-  // then the rows below both panels take both rank-NB updates in one pass
-  // over their C entries (half the trailing traffic of one pass per
-  // panel).  B's interchanges reach the pending rows and A's L rows alike,
-  // so they commute with A's deferred update, and every entry receives the
-  // same products in the same order as with one pass per panel.
+  // Grouped blocking (the form whose A21 is read back from global memory):
+  // panels go in groups of kGroup.  After each panel, the group's remaining
+  // columns take its update at once, as in one-level blocking; the columns
+  // beyond the group wait: per chunk of them, the panel's rows take the
+  // group's earlier panels' updates and are solved for its U12 rows, and
+  // after the group's last panel the rows below the group take all of the
+  // group's updates in one register pass over their C entries (a fraction
+  // of the trailing traffic of one pass per panel).  A panel's interchanges
+  // reach the pending rows and the group's earlier L rows alike, so they
+  // commute with the deferred updates, and every entry receives the same
+  // products in the same order as with one pass per panel.
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int kWaves = BT / kWave, kSB = kUC / 16;
   const int li = lane & 15, lq = lane >> 4;
@@ -204,12 +206,12 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     }
   };
   // rows [r0, r1) of the columns [col0, col0 + cw) minus A21_p U_p for the
-  // np panels p at columns jA (U in the first buffer) and jB (the second),
+  // np panels p at columns s0 + p NB (U_p in buffer p),
   // on the matrix cores: wave w takes the 16-row bands w, w + 8, ...; per
   // band and panel a lane loads its A21 fragments (from the panel stored
   // just before, still in cache) once for all of the chunk's 16-column
   // blocks, and every C load of the band is issued before the first product
-  auto c_update = [&](int r0, int r1, int col0, int cw, int np, int jA, int jB) {
+  auto c_update = [&](int r0, int r1, int col0, int cw, int np, int s0) {
     const int R = r1 - r0;
     const int nrb = (R + 15) / 16, nsb = (cw + 15) / 16;
     T* const C = A + (size_t)r0 * lda + col0;
@@ -226,7 +228,7 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
         }
       }
       for (int p = 0; p < np; ++p) {
-        const T* const A21 = A + (size_t)r0 * lda + (p == 0 ? jA : jB);
+        const T* const A21 = A + (size_t)r0 * lda + s0 + p * NB;
         const T* const U = L.U + p * NB * kUC;
         T af[NB / 4];
 #pragma unroll
@@ -472,34 +474,34 @@ __device__ __forceinline__ void factor_one(int n, T* __restrict__ A, int lda, in
     }
     __syncthreads();   // P, and the interchanged columns, visible to the workgroup
     if constexpr (!kPL) {
-      // 3, two-level: j is panel A or panel B of its pair
-      if (((j / NB) & 1) == 0) {
-        const int jb = j + nb, nbB = min(NB, n - jb), cS = jb + nbB;
-        // B's columns: A's U12 rows, then A's update of the rows below A
-        for (int c0 = jb; c0 < cS; c0 += kUC) {
-          const int cw = min(kUC, cS - c0);
-          solve_u12(j, c0, cw, L.U);
-          __syncthreads();
-          c_update(jb, n, c0, cw, 1, j, j);
-          __syncthreads();
-        }
-        // A's U12 rows of the columns beyond the pair, in place
-        for (int c0 = cS; c0 < n; c0 += kUC) solve_u12(j, c0, min(kUC, n - c0), nullptr);
+      // 3, grouped: panel q of the group starting at column s0
+      const int q = (j / NB) % kGroup, s0 = j - q * NB;
+      const int e = min(s0 + kGroup * NB, n);   // end of the group's columns
+      const bool last = j + nb >= e;
+      // the group's remaining columns: this panel's U12 rows, then its update
+      for (int c0 = j + nb; c0 < e; c0 += kUC) {
+        const int cw = min(kUC, e - c0);
+        solve_u12(j, c0, cw, L.U);
         __syncthreads();
-      } else {
-        const int ja = j - NB, cS = j + nb;
-        for (int c0 = cS; c0 < n; c0 += kUC) {
-          const int cw = min(kUC, n - c0);
-          for (int e = tid; e < NB * kUC; e += BT) {   // A's U12 rows of the chunk
-            const int k = e / kUC, c = e % kUC;
-            L.U[e] = c < cw ? A[(size_t)(ja + k) * lda + c0 + c] : T(0);
+        c_update(j + nb, n, c0, cw, 1, j);
+        __syncthreads();
+      }
+      // the columns beyond the group
+      for (int c0 = e; c0 < n; c0 += kUC) {
+        const int cw = min(kUC, n - c0);
+        if (q > 0) {
+          for (int x = tid; x < q * NB * kUC; x += BT) {   // the earlier panels' U12 rows of the chunk
+            const int p = x / (NB * kUC), k = (x / kUC) % NB, c = x % kUC;
+            L.U[x] = c < cw ? A[(size_t)(s0 + p * NB + k) * lda + c0 + c] : T(0);
           }
           __syncthreads();
-          c_update(j, cS, c0, cw, 1, ja, ja);   // B's rows: A's update
+          c_update(j, j + nb, c0, cw, q, s0);   // this panel's rows: their deferred updates
           __syncthreads();
-          solve_u12(j, c0, cw, L.U + NB * kUC);   // then B's U12 rows
-          __syncthreads();
-          c_update(cS, n, c0, cw, 2, ja, j);   // the rows below both: both updates
+        }
+        solve_u12(j, c0, cw, last ? L.U + q * NB * kUC : nullptr);
+        __syncthreads();
+        if (last) {
+          c_update(j + nb, n, c0, cw, q + 1, s0);   // the rows below the group: all its updates
           __syncthreads();
         }
       }
