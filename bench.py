@@ -198,7 +198,8 @@ def batched_section(args, dev):
     rng = np.random.default_rng(0)
     ns = rng.integers(8, 513, args.batch)
     flops = float(np.sum(2.0 * ns.astype(np.float64) ** 3 / 3.0))
-    out = {"batch": int(args.batch), "n_range": [8, 512], "matrix": "A = B B^T + n I, B ~ N(0,1) per matrix",
+    out = {"batch": int(args.batch), "n_range": [8, 512],
+           "matrix": "A = B B^T + n I, B ~ N(0,1) per matrix" + (" (host-built)" if args.batch_host_inputs else ""),
            "gflop": round(flops / 1e9, 3)}
     for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
         log(f"batched {name}: generating {args.batch} matrices")
@@ -206,14 +207,21 @@ def batched_section(args, dev):
         buf = torch.empty(int(offs[-1]), dtype=dt, device=dev)
         g = torch.Generator(device=dev)
         g.manual_seed(1)
+        hg = np.random.default_rng(1)
         for n in np.unique(ns):
             idx = np.nonzero(ns == n)[0]
-            b = torch.randn(len(idx), int(n), int(n), generator=g, dtype=torch.float64, device=dev)
-            a = torch.bmm(b, b.transpose(1, 2).contiguous())
+            if args.batch_host_inputs:   # no vendor GEMM in the process (counter runs)
+                hb = hg.standard_normal((len(idx), int(n), int(n)))
+                a = torch.from_numpy(hb @ hb.transpose(0, 2, 1)).to(dev)
+                del hb
+            else:
+                b = torch.randn(len(idx), int(n), int(n), generator=g, dtype=torch.float64, device=dev)
+                a = torch.bmm(b, b.transpose(1, 2).contiguous())
+                del b
             a.diagonal(dim1=1, dim2=2).add_(float(n))
             for t, i in enumerate(idx):
                 buf[int(offs[i]):int(offs[i + 1])].copy_(a[t].reshape(-1))
-            del a, b
+            del a
         pristine = buf.clone()
         mats = [buf[int(offs[i]):int(offs[i + 1])].view(int(n), int(n)) for i, n in enumerate(ns)]
         torch.cuda.synchronize()
@@ -599,6 +607,9 @@ def main() -> int:
     ap.add_argument("--grid", action="store_true",
                     help="also time every variant at n in {4096, 8192, 16384} x nb in {64, 128, 256}")
     ap.add_argument("--batch", type=int, default=20000)
+    ap.add_argument("--batch-host-inputs", action="store_true",
+                    help="build the batched inputs on the host (B B^T in numpy, another random stream), so that "
+                         "no vendor GEMM runs in the process; for counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise 1 GiB -> 1 GiB copy (reference kernel for HBM counters)")
     args = ap.parse_args()
