@@ -60,6 +60,22 @@ namespace {
 constexpr int NT = 512;   // threads per workgroup
 constexpr int NWAVE = NT / kWave;
 constexpr int U = 4;      // columns per rolled step
+
+// Instrumented builds (MLU_PANEL_PROBE, a separate library, never the product
+// one) record real-time stamps of the exact-mode column step of the first and
+// the last worker: [worker][column % 64][phase], phases 0 column start, 1
+// local argmax done, 2 poll issued, 3 poll complete, 4 barrier passed, 5 row
+// update done.
+#ifdef MLU_PANEL_PROBE
+}  // namespace
+__device__ unsigned long long g_probe_stamps[2][64][6];
+namespace {
+__device__ __forceinline__ void probe_stamp(int who, int c, int k, int tid) {
+  if (who >= 0 && tid == 0) g_probe_stamps[who][c & 63][k] = __builtin_amdgcn_s_memrealtime();
+}
+#else
+__device__ __forceinline__ void probe_stamp(int, int, int, int) {}
+#endif
 constexpr long long kSpinLimit = 1LL << 21;
 constexpr int kRowNone = INT_MAX;
 constexpr int kSc1 = 16;  // buffer cache policy of the publishing stores: device-coherent
@@ -408,9 +424,12 @@ struct Panel {
         constexpr int par = u & 1;
         const int c = c0 + u;
         if (c < bw) {
+          const int who = wg == 0 ? 0 : (wg == nwg - 1 ? 1 : -1);
+          probe_stamp(who, c, 0, tid);
           double bv;
           int br, wbest;
           local_best<u, par>(c, bv, br, wbest);
+          probe_stamp(who, c, 1, tid);
           int p = br;
           const double* prow = s_cand[par][wbest];
           if (nwg > 1) {
@@ -430,7 +449,9 @@ struct Panel {
                 const int f = min(lane + kWave * i, nwg * BW - 1);
                 offs[2 + i] = off_cand(par, f / BW, f % BW);
               }
+              probe_stamp(who, c, 2, tid);
               poll_chunks<kPoll + 2>(wbase, offs, got, tag, lane, info);
+              probe_stamp(who, c, 3, tid);
               double gv = lane < nwg ? chunk_val(got[0]) : -1.0;
               int gr = lane < nwg ? got[0][2] : kRowNone;
               wave_argmax(gv, gr);
@@ -444,10 +465,12 @@ struct Panel {
               if (lane < BW) s_drow[par][lane] = chunk_val(got[1]);
             }
             lds_sync();
+            probe_stamp(who, c, 4, tid);
             p = sh->p[par];
             prow = s_prow[par];
           }
           apply<u>(c, lim, p, prow, s_drow[par]);
+          probe_stamp(who, c, 5, tid);
         }
       });
       rotate();
@@ -872,3 +895,11 @@ hipError_t panel_factor(hipStream_t s, double* A, int lda, int m, int bw, int ro
 size_t workspace_bytes() { return (sizeof(Workspace) + 4095) / 4096 * 4096; }
 
 }  // namespace mlu
+
+#ifdef MLU_PANEL_PROBE
+// The stamps of the last instrumented panel call (2 x 64 x 6 values).
+extern "C" int mlu_probe_stamps(unsigned long long* host) {
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(mlu::g_probe_stamps), sizeof(mlu::g_probe_stamps)) == hipSuccess ? 0
+                                                                                                             : -1;
+}
+#endif
