@@ -616,8 +616,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build factors one matrix per GPU and has no "
-              "multi-GPU path (see the sharding notes in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library factors each matrix on one GPU and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
