@@ -16,8 +16,8 @@
  *  * `stream` is a hipStream_t (NULL = the default stream).  All device work is
  *    enqueued on it asynchronously; nothing synchronizes, except the two entry
  *    points whose loop is decided on the host (mlu_dgetrf_et waits for each
- *    panel's realized width, mlu_dsgesv_gmres_ir for each refinement and GMRES
- *    step), as documented there.  Results (including *d_info) are valid once
+ *    panel's realized width, mlu_dsgesv_gmres_ir for each refinement and each
+ *    chunk of GMRES steps), as documented there.  Results (including *d_info) are valid once
  *    the stream's work has completed.  The look-ahead
  *    variant additionally uses one library-owned stream per device (default
  *    priority), forked from and joined back into `stream` with events, so a

@@ -38,6 +38,10 @@ constexpr double kDivergeFactor = 2.0;
 // GMRES-IR gives up after this many GMRES corrections in a row that each fail
 // to halve the backward error.
 constexpr int kGmresStalls = 2;
+// The host enqueues Arnoldi steps in chunks of 1, 2, 4, 4, ... and reads the
+// state once per chunk; a device flag set by the step that meets the GMRES
+// tolerance makes the chunk's later steps return at once.
+constexpr int kGmresChunkMax = 4;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
@@ -250,7 +254,8 @@ __global__ __launch_bounds__(256) void k_perm_from_ipiv(int n, const int32_t* __
 
 // Out[i] := X[perm[i]] (one right-hand side)
 __global__ void k_gather(int n, const int32_t* __restrict__ perm, const double* __restrict__ X,
-                         double* __restrict__ Out) {
+                         double* __restrict__ Out, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) Out[i] = X[perm[i]];
 }
 
@@ -277,7 +282,7 @@ hipError_t getrs_blocked(hipStream_t s, int n, int nrhs, const double* LU, int l
   double* Y = Bx;
   int ldy = ldb;
   if (perm != nullptr && nrhs == 1) {
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)min((n + 255) / 256, 65536)), dim3(256), 0, s, n, perm, Bx, ybuf);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)min((n + 255) / 256, 65536)), dim3(256), 0, s, n, perm, Bx, ybuf, skip);
     MLU_IR_TRY(hipGetLastError());
     Y = ybuf;
     ldy = 1;
@@ -386,14 +391,16 @@ struct GmresState {
   double beta;    // ||z||_2 of the current correction's right-hand side
   double hnext;   // h(k+1, k) of the last Arnoldi step, before its rotation
   double resid;   // |g(k+1)|: GMRES residual norm after the last step
+  int32_t stop;   // set by the Arnoldi step that ends the correction; later steps' kernels skip
+  int32_t steps;  // Arnoldi steps made in the current correction
 };
 
 // out[j] = V_j . w for j < k (one workgroup per j, fixed-order reduction)
 __global__ __launch_bounds__(256) void k_dots(int n, int k, const double* __restrict__ V, const double* __restrict__ w,
-                                              double* __restrict__ out) {
+                                              double* __restrict__ out, const int32_t* __restrict__ skip) {
   __shared__ double part[4];
   const int j = blockIdx.x;
-  if (j >= k) return;
+  if (j >= k || (skip != nullptr && *skip != 0)) return;
   const double* v = V + (size_t)j * n;
   double s4[4] = {0.0, 0.0, 0.0, 0.0};   // four strided partial sums: four loads in flight
   int i = threadIdx.x;
@@ -418,7 +425,8 @@ __global__ __launch_bounds__(256) void k_dots(int n, int k, const double* __rest
 // w[i] += sign * sum_{j<k} V_j[i] h[j]  (the sum first, then one update)
 __global__ __launch_bounds__(256) void k_basis_combine(int n, int k, const double* __restrict__ V,
                                                        const double* __restrict__ h, double sign,
-                                                       double* __restrict__ w) {
+                                                       double* __restrict__ w, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   __shared__ double hs[kGmresMaxKrylov + 1];
   for (int j = threadIdx.x; j < k; j += 256) hs[j] = h[j];
   __syncthreads();
@@ -430,7 +438,9 @@ __global__ __launch_bounds__(256) void k_basis_combine(int n, int k, const doubl
 }
 
 // v[i] := v[i] / *div
-__global__ void k_div_by(int n, double* __restrict__ v, const double* __restrict__ div) {
+__global__ void k_div_by(int n, double* __restrict__ v, const double* __restrict__ div,
+                         const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
   const double d = *div;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = v[i] / d;
 }
@@ -440,17 +450,21 @@ __global__ void k_gmres_start(GmresState* st, const double* __restrict__ zz, dou
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double beta = sqrt(*zz);
   st->beta = beta;
+  st->stop = 0;
+  st->steps = 0;
   g[0] = beta;
   for (int i = 1; i <= m; ++i) g[i] = 0.0;
 }
 
 // one thread: Arnoldi step k's column of H from the two Gram-Schmidt rounds
 // (h1 + h2) and ||w||_2, the earlier rotations applied to it, a new rotation
-// that zeroes h(k+1, k), and the rotated right-hand side g.
+// that zeroes h(k+1, k), and the rotated right-hand side g.  The step that
+// brings the GMRES residual to tol * beta, or meets a zero h(k+1, k) (an
+// invariant Krylov space), sets the stop flag.
 __global__ void k_arnoldi(GmresState* st, int k, int m, const double* __restrict__ h1, const double* __restrict__ h2,
                           const double* __restrict__ ww, double* __restrict__ H, double* __restrict__ cs,
-                          double* __restrict__ sn, double* __restrict__ g) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                          double* __restrict__ sn, double* __restrict__ g, double tol) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || st->stop != 0) return;
   double* col = H + (size_t)k * (m + 1);
   for (int j = 0; j <= k; ++j) col[j] = h1[j] + h2[j];
   const double hnext = sqrt(*ww);
@@ -471,6 +485,8 @@ __global__ void k_arnoldi(GmresState* st, int k, int m, const double* __restrict
   g[k + 1] = -s * g[k];
   g[k] = c * g[k];
   st->resid = fabs(g[k + 1]);
+  st->steps = k + 1;
+  if (st->resid <= tol * st->beta || !(hnext > 0.0)) st->stop = 1;
 }
 
 // one thread: y = R^-1 g over the first `steps` columns of the rotated H
@@ -727,10 +743,10 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
   hipLaunchKernelGGL(k_perm_from_ipiv, dim3(1), dim3(256), 0, s, n, d_ipiv, perm);
   if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-  const auto precondition = [&](double* v) {   // v := M^-1 v
-    return getrs_blocked(s, n, 1, LU, n, d_ipiv, ib, Linv, Uinv, v, 1, T, nullptr, perm, Yb);
+  const auto precondition = [&](double* v, const int32_t* skip) {   // v := M^-1 v
+    return getrs_blocked(s, n, 1, LU, n, d_ipiv, ib, Linv, Uinv, v, 1, T, skip, perm, Yb);
   };
-  if (precondition(dx) != hipSuccess) return MLU_ERR_HIP;
+  if (precondition(dx, nullptr) != hipSuccess) return MLU_ERR_HIP;
 
   const unsigned gc = (unsigned)((n + 255) / 256);
   bool gmres_mode = solver == MLU_IR_GMRES;
@@ -775,41 +791,45 @@ int mlu_dsgesv_gmres_ir(void* stream, int n, const double* dA, int lda, const do
     // z := M^-1 r, into the first basis vector
     hipLaunchKernelGGL(k_ir_copy, dim3(g1), dim3(256), 0, s, n, 1, R, 1, V, 1, nullptr);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
-    if (precondition(V) != hipSuccess) return MLU_ERR_HIP;
+    if (precondition(V, nullptr) != hipSuccess) return MLU_ERR_HIP;
     if (!gmres_mode) {   // LU-IR: x := x + z
       hipLaunchKernelGGL(k_ir_axpy, dim3(g1), dim3(256), 0, s, n, 1, V, 1, dx, 1, nullptr);
       if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
       continue;
     }
     // GMRES on M^-1 A d = z from d = 0
-    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, V, V, ww);
+    hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, V, V, ww, nullptr);
     hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(64), 0, s, st, ww, g, m);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
     if (read_state(s, st, &hs) != hipSuccess) return MLU_ERR_HIP;
     if (!(hs.beta > 0.0)) continue;   // z = 0 (or not finite): no correction to make
-    const double beta = hs.beta;
-    hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, V, &st->beta);
-    int steps = 0;
-    for (int k = 0; k < m; ++k) {
-      double* w = V + (size_t)(k + 1) * n;   // the next basis vector, built in place
-      if (gemv(s, n, n, 1, dA, lda, V + (size_t)k * n, 1, nullptr, 0, w, 1, nullptr) != hipSuccess)
-        return MLU_ERR_HIP;
-      if (precondition(w) != hipSuccess) return MLU_ERR_HIP;
-      hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h1);
-      hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h1, -1.0, w);
-      hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h2);
-      hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h2, -1.0, w);
-      hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, w, w, ww);
-      hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, st, k, m, h1, h2, ww, H, cs, sn, g);
-      if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+    hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, V, &st->beta, nullptr);
+    // Arnoldi steps, enqueued a chunk at a time; every kernel of a step after
+    // the one that sets the stop flag returns at once
+    const int32_t* stop = &st->stop;
+    int k = 0;
+    for (int chunk = 1; k < m; chunk = std::min(2 * chunk, kGmresChunkMax)) {
+      for (const int kend = std::min(m, k + chunk); k < kend; ++k) {
+        double* w = V + (size_t)(k + 1) * n;   // the next basis vector, built in place
+        if (gemv(s, n, n, 1, dA, lda, V + (size_t)k * n, 1, nullptr, 0, w, 1, stop) != hipSuccess)
+          return MLU_ERR_HIP;
+        if (precondition(w, stop) != hipSuccess) return MLU_ERR_HIP;
+        hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h1, stop);
+        hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h1, -1.0, w, stop);
+        hipLaunchKernelGGL(k_dots, dim3(k + 1), dim3(256), 0, s, n, k + 1, V, w, h2, stop);
+        hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, k + 1, V, h2, -1.0, w, stop);
+        hipLaunchKernelGGL(k_dots, dim3(1), dim3(256), 0, s, n, 1, w, w, ww, stop);
+        hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, st, k, m, h1, h2, ww, H, cs, sn, g, gmres_tol);
+        hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, w, &st->hnext, stop);
+        if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
+      }
       if (read_state(s, st, &hs) != hipSuccess) return MLU_ERR_HIP;
-      steps = k + 1;
-      if (hs.resid <= gmres_tol * beta || !(hs.hnext > 0.0)) break;
-      hipLaunchKernelGGL(k_div_by, dim3(g1), dim3(256), 0, s, n, w, &st->hnext);
+      if (hs.stop != 0) break;
     }
+    const int steps = hs.steps;
     // d = V y, x := x + d
     hipLaunchKernelGGL(k_hess_solve, dim3(1), dim3(64), 0, s, steps, m, H, g, y);
-    hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, steps, V, y, 1.0, dx);
+    hipLaunchKernelGGL(k_basis_combine, dim3(gc), dim3(256), 0, s, n, steps, V, y, 1.0, dx, nullptr);
     if (hipGetLastError() != hipSuccess) return MLU_ERR_HIP;
     inner += steps;
   }
