@@ -166,17 +166,16 @@ __global__ __launch_bounds__(256) void k_gemv(int rows, int cols, int nrhs, cons
   }
 }
 
-// One right-hand side with A and x on 16-byte boundaries (lda even, x
-// contiguous): the same one-wave-per-row product, each lane loading two
-// neighbouring elements of the row and of x per 16-byte load, four such loads
-// in flight, and A's loads marked non-temporal (each element of A is read
+// One right-hand side with x contiguous: the same one-wave-per-row product,
+// each lane loading two neighbouring elements of the row and of x per 16-byte
+// load (which needs only 8-byte alignment, so rows of an odd lda keep it),
+// four such loads in flight, and A's loads marked non-temporal (each element of A is read
 // once per product, so it need not displace x from the caches).  Moving 16
 // bytes per lane per load instead of 8 takes the n = 16384 product from about
 // 5.1 to 6.5 TB/s and the 1024-column block steps of the triangular solves
 // from about 4.3 to 5.4 TB/s.  A lane accumulates even and odd elements
 // apart and adds the two before the wave sum; an odd last column is added
 // by lane 0.
-typedef double dbl2 __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_gemv_x2(int rows, int cols, const double* __restrict__ A, int lda,
                                                  const double* __restrict__ X, const double* Y, int ldy,
                                                  double* Out, int ldo, const int32_t* __restrict__ skip) {
@@ -184,13 +183,13 @@ __global__ __launch_bounds__(256) void k_gemv_x2(int rows, int cols, const doubl
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  const dbl2* a = reinterpret_cast<const dbl2*>(A + (size_t)row * lda);
-  const dbl2* x = reinterpret_cast<const dbl2*>(X);
+  const dbl2_g* a = reinterpret_cast<const dbl2_g*>(A + (size_t)row * lda);
+  const dbl2_g* x = reinterpret_cast<const dbl2_g*>(X);
   const int pairs = cols >> 1;
   double s0 = 0.0, s1 = 0.0;
   int j = lane;
   for (; j + 192 < pairs; j += 256) {
-    dbl2 av[4], xv[4];
+    dbl2_g av[4], xv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       av[u] = __builtin_nontemporal_load(a + j + 64 * u);
@@ -203,7 +202,7 @@ __global__ __launch_bounds__(256) void k_gemv_x2(int rows, int cols, const doubl
     }
   }
   for (; j < pairs; j += 64) {
-    const dbl2 av = a[j], xv = x[j];
+    const dbl2_g av = a[j], xv = x[j];
     s0 += av.x * xv.x;
     s1 += av.y * xv.y;
   }
@@ -219,8 +218,8 @@ hipError_t gemv(hipStream_t s, int rows, int cols, int nrhs, const double* A, in
                 const double* Y, int ldy, double* Out, int ldo, const int32_t* skip) {
   if (rows <= 0 || nrhs <= 0) return hipSuccess;
   const dim3 grid((unsigned)((rows + 3) / 4)), block(256);
-  const bool x2 = nrhs == 1 && (lda & 1) == 0 && ldx == 1 &&
-                  ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(X)) & 15) == 0;
+  const bool x2 = nrhs == 1 && ldx == 1 &&
+                  ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(X)) & 7) == 0;
   if (x2)
     hipLaunchKernelGGL(k_gemv_x2, grid, block, 0, s, rows, cols, A, lda, X, Y, ldy, Out, ldo, skip);
   else if (nrhs == 1)

@@ -122,6 +122,46 @@ def test_gesv_ir_reaches_fp64_backward_error(cond, nrhs, variant):
     assert fwd <= cond * 1e-12
 
 
+@pytest.mark.parametrize("layout", ["odd_order", "padded_odd_lda", "strided_rhs"])
+def test_gesv_ir_operand_views(layout):
+    """Operands as views of larger arrays.  odd_order: A contiguous with n odd
+    (odd lda, odd row length); padded_odd_lda: n even inside rows of odd length
+    (the one-right-hand-side product loads 16 bytes from rows that start off
+    16-byte boundaries); strided_rhs: B and X single columns of n x 3 arrays
+    (a strided x takes the 8-byte product).  Same bars as above."""
+    n = 517 if layout == "odd_order" else 516
+    cond = 1e5
+    A = G.haar_spectrum(n, cond, seed=5)
+    B = G.gaussian_rhs(n, 1, seed=3)
+    dX = None
+    if layout == "padded_odd_lda":
+        big = np.zeros((n, n + 1))
+        big[:, :n] = A
+        dA, dB = dev(big)[:, :n], dev(B)
+        assert dA.stride(0) == n + 1
+    elif layout == "strided_rhs":
+        wide = np.zeros((n, 3))
+        wide[:, 2:] = B
+        dA, dB = dev(A), dev(wide)[:, 2:]
+        dX = torch.zeros((n, 3), dtype=torch.float64, device=DEV)[:, 1:2]
+        assert dB.stride(0) == 3 and dX.stride(0) == 3
+    else:
+        dA, dB = dev(A), dev(B)
+    X, ipiv, info, iters, berr = mlu.gesv_ir(dA, dB, precision="fp32", tol=1e-13, max_iter=10, variant="la",
+                                             nb=64, X=dX)
+    Xh = host(X)
+    it, be = int(host(iters)[0]), float(host(berr)[0])
+    hb = backward_error(A, Xh, B)
+    X64 = oracle_solution(("views", layout), A, B)
+    fwd = np.abs(Xh - X64).max() / np.abs(X64).max()
+    print(f"gesv_ir fp32 {layout} n={n}: iters {it}, berr {be:.2e} (host {hb:.2e}), |x - x64|/|x64| {fwd:.2e}",
+          flush=True)
+    assert int(host(info)[0]) == 0
+    assert 0 <= it <= 10
+    assert be <= 1e-13 and hb <= 2e-13
+    assert fwd <= cond * 1e-12
+
+
 def test_gesv_ir_fp64_needs_at_most_one_correction():
     n = 500
     A = G.uniform01(n, seed=9)
