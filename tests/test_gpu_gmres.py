@@ -70,7 +70,7 @@ def solve(A, b, **kw):
 
 @pytest.mark.parametrize("n,cond,precision,solver,variant,nb", [
     (300, 1e2, "fp32", "gmres", "la", 64),
-    (301, 1e2, "fp32", "gmres", "la", 64),   # odd order: 8-byte product form over A and LU, odd-width last block
+    (301, 1e2, "fp32", "gmres", "la", 64),   # odd order: rows off 16-byte boundaries, odd-width last block
     (300, 1e8, "fp32", "gmres", "la", 64),
     (700, 1e8, "fp32", "gmres", "rl", 128),
     (700, 1e8, "fp32", "auto", "la", 128),
